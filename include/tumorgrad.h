@@ -1,0 +1,145 @@
+/*
+ * tumorgrad: forward, adjoint and Gauss-Newton Hessian solves of the
+ * reaction-diffusion tumor-growth model used for image-driven model
+ * calibration (Scheufele, Subramanian, Mang, Biros, Mehl, "Image-driven
+ * biophysical tumor growth model calibration", arXiv:1907.07774).
+ *
+ * Model (Sec. 2.1, tumor forward operator with the white-matter-only
+ * coefficients of Sec. 4.1), on the periodic cube [0, 2 pi)^3:
+ *     dc/dt = div(k_f m grad c) + rho_f m c (1 - c),   c(0) = Phi p,
+ * with Phi p = sum_i p_i exp(-|x - x_i|^2 / (2 sigma^2)) (periodic minimum
+ * image distance, peak value 1).  Discretization (Sec. 3.3): Fourier
+ * pseudo-spectral derivatives on an n^3 grid (Nyquist wavenumber of first
+ * derivatives set to zero), Strang splitting of nt steps over [0, T] with
+ * the exact logistic reaction flow on half steps and Crank-Nicolson
+ * diffusion solved by PCG with the preconditioner
+ * (1 + dt/2 k_f max(m) |w|^2)^-1.  The misfit is the tumor L2 distance of
+ * Tab. 1, J = 1/2 h^3 sum (c(T) - c_obs)^2, h = 2 pi / n.  Gradients are the
+ * exact derivatives of the discrete map (the reduced gradient of Sec. 3.1:
+ * state solve, adjoint solve, gradient), with respect to p (Sec. 2.1,
+ * p-gradient Phi^T alpha(0)), k_f (Sec. 2.1, diffusion-coefficient
+ * gradient) and rho_f.
+ *
+ * Conventions for every entry point:
+ *   - Real fields are C-contiguous [n][n][n] arrays (x slowest, z fastest)
+ *     of double (TG_FP64) or float (TG_FP32_MIXED).  With batch B > 1 the
+ *     problems are stacked: field b starts at element b n^3.
+ *   - Parameter vectors (p, rho_f, k_f, gradients) are double in both
+ *     precisions, stacked per problem (p: [B][n_p], rho_f and k_f: [B]).
+ *   - All array arguments are DEVICE pointers owned by the caller; the
+ *     library never allocates or frees device memory.  Its only device
+ *     storage is the workspace given to tg_plan_bind.
+ *   - stream is a hipStream_t passed as void*.  Work is enqueued on it; the
+ *     PCG loops synchronize that stream between blocks of iterations to
+ *     read convergence flags, so calls return after the solves finished
+ *     and only the final, non-iterative kernels may still be in flight.
+ *   - Argument, state and workspace errors are detected on the host before
+ *     anything is launched.  A PCG that hits pcg_maxit, breaks down or
+ *     produces non-finite values still writes all outputs and the call
+ *     returns TG_ERR_NOT_CONVERGED / TG_ERR_NUMERIC.
+ *   - One plan is used by one stream at a time.
+ */
+#ifndef TUMORGRAD_H
+#define TUMORGRAD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TG_OK = 0,
+  TG_ERR_ARG = 1,            /* invalid argument or descriptor */
+  TG_ERR_STATE = 2,          /* call order violated (e.g. vjp before forward) */
+  TG_ERR_NOT_CONVERGED = 3,  /* a PCG solve reached pcg_maxit */
+  TG_ERR_NUMERIC = 4,        /* PCG breakdown or non-finite values */
+  TG_ERR_HIP = 5,            /* a HIP runtime call or kernel launch failed */
+  TG_ERR_WORKSPACE = 6       /* workspace missing, too small or misaligned */
+} tg_status;
+
+typedef enum {
+  TG_FP64 = 0,        /* all fields, transforms and reductions in double */
+  TG_FP32_MIXED = 1   /* float fields and transforms; double dots, norms,
+                         PCG scalars and gradient accumulation */
+} tg_precision;
+
+typedef struct tg_desc {
+  int n;                 /* grid points per axis: 8, 16, 32, 64, 128 or 256 */
+  int nt;                /* Strang steps, >= 1 */
+  double T;              /* time horizon, > 0 (dt = T / nt) */
+  int n_p;               /* Gaussian basis functions per problem, 1..4096 */
+  const double* centres; /* HOST [batch][n_p][3] centres in [0, 2 pi)^3,
+                            copied at tg_plan_bind */
+  double sigma;          /* Gaussian standard deviation, > 0 */
+  double pcg_rtol;       /* PCG stop: ||r|| <= rtol ||rhs||, 0 < rtol < 1.
+                            TG_FP32_MIXED stops no lower than 50 eps_32. */
+  int pcg_maxit;         /* >= 1 */
+  int ckpt_stride;       /* 0: keep every step's state; s > 0: keep every
+                            s-th state and recompute segments in the adjoint */
+  tg_precision prec;
+  int batch;             /* independent problems solved together, >= 1 */
+  int max_hvp_dirs;      /* Hessian directions per tg_hessvec_gn call, >= 0 */
+} tg_desc;
+
+typedef struct tg_solve_stats {
+  int solves;               /* CN solves in the last call */
+  int pcg_its_total;        /* PCG iterations summed over those solves */
+  int pcg_its_max;          /* largest iteration count of one solve */
+  int status_bits;          /* 1: maxit reached, 2: breakdown, 4: non-finite */
+  double worst_rel_residual;/* max over solves of final ||r|| / ||rhs|| */
+} tg_solve_stats;
+
+typedef struct tg_plan tg_plan;
+
+/* Validate a descriptor and create a plan (host memory only; nothing is
+ * launched).  Errors: TG_ERR_ARG. */
+tg_status tg_plan_create(const tg_desc* desc, tg_plan** out);
+
+/* Bytes of device workspace the plan needs (256-byte aligned buffer). */
+tg_status tg_plan_workspace_bytes(const tg_plan* plan, size_t* bytes);
+
+/* Bind caller-owned device memory as workspace, on the current device.
+ * Copies the centres and fills the device twiddle table (synchronous).
+ * Errors: TG_ERR_WORKSPACE (null, misaligned, too small), TG_ERR_HIP. */
+tg_status tg_plan_bind(tg_plan* plan, void* d_workspace, size_t bytes);
+
+/* Forward solve (state equation, Sec. 2.1; discretization Sec. 3.3):
+ * c(T) from p [B][n_p], rho_f [B], k_f [B], white-matter map m [B][n^3].
+ * Writes d_cT [B][n^3].  m, p, rho_f, k_f and cT must stay valid and
+ * unchanged until the last tg_vjp / tg_adjoint_misfit / tg_hessvec_gn that
+ * uses this trajectory. */
+tg_status tg_forward(tg_plan* plan, const double* d_p, const double* d_rho_f,
+                     const double* d_k_f, const void* d_m, void* d_cT, void* stream);
+
+/* Vector-Jacobian product of the last forward (adjoint solve, Sec. 2.1
+ * optimality conditions, evaluated as in Sec. 3.1): given a Euclidean
+ * cotangent lamT [B][n^3] on c(T), writes g_p = d<lamT, c(T)>/dp [B][n_p],
+ * g_rho [B] and g_kf [B].  Errors: TG_ERR_STATE before any tg_forward. */
+tg_status tg_vjp(tg_plan* plan, const void* d_lamT, double* d_gp, double* d_grho,
+                 double* d_gkf, void* stream);
+
+/* Misfit J = 1/2 h^3 sum (c(T) - c_obs)^2 (tumor misfit of Tab. 1) and its
+ * gradient: tg_vjp with lamT = h^3 (c(T) - c_obs).  Writes d_J [B]. */
+tg_status tg_adjoint_misfit(tg_plan* plan, const void* d_cobs, double* d_J, double* d_gp,
+                            double* d_grho, double* d_gkf, void* stream);
+
+/* Gauss-Newton Hessian of J with respect to p about the last forward
+ * trajectory (batch must be 1): HV[d] = Phi^T J_c^T h^3 J_c Phi V[d] for
+ * d < ndir, V and HV [ndir][n_p].  Tangent-linear forward plus adjoint,
+ * all directions batched per launch.  Errors: TG_ERR_ARG (ndir outside
+ * 1..max_hvp_dirs or batch > 1), TG_ERR_STATE. */
+tg_status tg_hessvec_gn(tg_plan* plan, int ndir, const double* d_V, double* d_HV,
+                        void* stream);
+
+/* PCG statistics of the last call (synchronizes the plan's last stream). */
+tg_status tg_stats(tg_plan* plan, tg_solve_stats* out);
+
+const char* tg_status_string(tg_status s);
+void tg_plan_destroy(tg_plan* plan);
+int tg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TUMORGRAD_H */

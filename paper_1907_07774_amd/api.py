@@ -1,0 +1,210 @@
+"""Python binding of libtumorgrad: plans, forward / gradient / Hessian calls
+and a torch.autograd.Function.
+
+PyTorch supplies device memory and the HIP stream; every step of the solve
+runs in the library's HIP kernels.  Functions here only check shapes and
+dtypes and pass pointers.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+
+import numpy as np
+import torch
+
+from . import _lib
+
+PRECISIONS = {"fp64": _lib.TG_FP64, "fp32": _lib.TG_FP32_MIXED}
+
+
+@dataclasses.dataclass
+class Stats:
+    solves: int
+    pcg_its_total: int
+    pcg_its_max: int
+    status_bits: int
+    worst_rel_residual: float
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """One grid size, horizon, basis and precision; ``batch`` independent
+    problems solved together.
+
+    centres: array [n_p, 3] (shared by the batch) or [batch, n_p, 3].
+    precision: "fp64" or "fp32" (FP32 fields and transforms with FP64
+    reductions).
+    """
+
+    def __init__(self, n: int, nt: int, centres, sigma: float, T: float = 1.0,
+                 rtol: float = 1e-8, maxit: int = 1000, ckpt_stride: int = 0,
+                 precision: str = "fp64", batch: int = 1, max_hvp_dirs: int = 0,
+                 device: str | torch.device = "cuda:0"):
+        L = _lib.lib()
+        cen = np.asarray(centres, dtype=np.float64)
+        if cen.ndim == 2:
+            cen = np.broadcast_to(cen, (batch,) + cen.shape)
+        cen = np.ascontiguousarray(cen)
+        if cen.shape[0] != batch or cen.shape[2] != 3:
+            raise ValueError(f"centres shape {cen.shape} does not match batch {batch}")
+        self.n, self.nt, self.T = int(n), int(nt), float(T)
+        self.n_p = int(cen.shape[1])
+        self.batch = int(batch)
+        self.max_hvp_dirs = int(max_hvp_dirs)
+        self.precision = precision
+        self.dtype = torch.float64 if precision == "fp64" else torch.float32
+        self.device = torch.device(device)
+        self._cen = cen
+        d = _lib.TgDesc(self.n, self.nt, self.T, self.n_p,
+                        cen.ctypes.data_as(C.POINTER(C.c_double)), float(sigma),
+                        float(rtol), int(maxit), int(ckpt_stride), PRECISIONS[precision],
+                        self.batch, self.max_hvp_dirs)
+        h = C.c_void_p()
+        _lib.check(L.tg_plan_create(C.byref(d), C.byref(h)), "tg_plan_create")
+        self._h = h
+        nbytes = C.c_size_t()
+        _lib.check(L.tg_plan_workspace_bytes(h, C.byref(nbytes)), "tg_plan_workspace_bytes")
+        self.workspace_bytes = int(nbytes.value)
+        self._ws = None
+        self._keep = ()
+        self.generation = 0
+
+    # ------------------------------------------------------------ plumbing
+    def _bind(self):
+        if self._ws is not None:
+            return
+        with torch.cuda.device(self.device):
+            ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+            off = (-ws.data_ptr()) % 256
+            self._ws = ws
+            _lib.check(_lib.lib().tg_plan_bind(self._h, C.c_void_p(ws.data_ptr() + off),
+                                                self.workspace_bytes), "tg_plan_bind")
+
+    def _stream(self):
+        return C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _field(self, x, name):
+        if not isinstance(x, torch.Tensor):
+            x = torch.as_tensor(np.asarray(x), device=self.device)
+        x = x.to(device=self.device, dtype=self.dtype).contiguous()
+        if x.numel() != self.batch * self.n ** 3:
+            raise ValueError(f"{name}: expected {self.batch} x {self.n}^3 values, got {x.numel()}")
+        return x
+
+    def _vec(self, x, count, name):
+        if not isinstance(x, torch.Tensor):
+            x = torch.as_tensor(np.asarray(x, dtype=np.float64), device=self.device)
+        x = x.to(device=self.device, dtype=torch.float64).contiguous()
+        if x.numel() != count:
+            raise ValueError(f"{name}: expected {count} values, got {x.numel()}")
+        return x
+
+    def _shape(self, t):
+        return t.view(self.n, self.n, self.n) if self.batch == 1 else \
+            t.view(self.batch, self.n, self.n, self.n)
+
+    # ---------------------------------------------------------------- calls
+    def forward(self, p, rho_f, k_f, m) -> torch.Tensor:
+        """c(T) for coefficients p, growth rates rho_f and k_f, WM map m."""
+        self._bind()
+        p = self._vec(p, self.batch * self.n_p, "p")
+        rho = self._vec(rho_f, self.batch, "rho_f")
+        kf = self._vec(k_f, self.batch, "k_f")
+        m = self._field(m, "m")
+        cT = torch.empty_like(m)
+        st = _lib.lib().tg_forward(self._h, _ptr(p), _ptr(rho), _ptr(kf), _ptr(m), _ptr(cT),
+                                   self._stream())
+        self._keep = (p, rho, kf, m, cT)
+        self.generation += 1
+        _lib.check(st, "tg_forward")
+        return self._shape(cT)
+
+    def vjp(self, lamT):
+        """(g_p, g_rho, g_kf) = d<lamT, c(T)>/d(p, rho_f, k_f) of the last forward."""
+        self._bind()
+        lam = self._field(lamT, "lamT")
+        gp = torch.empty(self.batch * self.n_p, dtype=torch.float64, device=self.device)
+        gr = torch.empty(self.batch, dtype=torch.float64, device=self.device)
+        gk = torch.empty(self.batch, dtype=torch.float64, device=self.device)
+        _lib.check(_lib.lib().tg_vjp(self._h, _ptr(lam), _ptr(gp), _ptr(gr), _ptr(gk),
+                                     self._stream()), "tg_vjp")
+        return self._vecs(gp, gr, gk)
+
+    def adjoint_misfit(self, c_obs):
+        """(J, g_p, g_rho, g_kf) of J = 1/2 h^3 sum (c(T) - c_obs)^2."""
+        self._bind()
+        d = self._field(c_obs, "c_obs")
+        J = torch.empty(self.batch, dtype=torch.float64, device=self.device)
+        gp = torch.empty(self.batch * self.n_p, dtype=torch.float64, device=self.device)
+        gr = torch.empty(self.batch, dtype=torch.float64, device=self.device)
+        gk = torch.empty(self.batch, dtype=torch.float64, device=self.device)
+        _lib.check(_lib.lib().tg_adjoint_misfit(self._h, _ptr(d), _ptr(J), _ptr(gp), _ptr(gr),
+                                                _ptr(gk), self._stream()), "tg_adjoint_misfit")
+        gp, gr, gk = self._vecs(gp, gr, gk)
+        return (J[0] if self.batch == 1 else J), gp, gr, gk
+
+    def hessvec(self, V) -> torch.Tensor:
+        """Gauss-Newton Hessian products H V[d] for V of shape [ndir, n_p]."""
+        self._bind()
+        V = torch.as_tensor(V, dtype=torch.float64, device=self.device).contiguous()
+        if V.ndim == 1:
+            V = V[None]
+        ndir = V.shape[0]
+        if V.shape[1] != self.n_p:
+            raise ValueError(f"V: expected [ndir, {self.n_p}], got {tuple(V.shape)}")
+        HV = torch.empty_like(V)
+        _lib.check(_lib.lib().tg_hessvec_gn(self._h, ndir, _ptr(V), _ptr(HV), self._stream()),
+                   "tg_hessvec_gn")
+        return HV
+
+    def stats(self) -> Stats:
+        s = _lib.TgSolveStats()
+        _lib.check(_lib.lib().tg_stats(self._h, C.byref(s)), "tg_stats")
+        return Stats(s.solves, s.pcg_its_total, s.pcg_its_max, s.status_bits,
+                     s.worst_rel_residual)
+
+    def _vecs(self, gp, gr, gk):
+        if self.batch == 1:
+            return gp, gr[0], gk[0]
+        return gp.view(self.batch, self.n_p), gr, gk
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                if self._ws is not None:
+                    torch.cuda.synchronize(self.device)
+                _lib.lib().tg_plan_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+
+class TumorSolve(torch.autograd.Function):
+    """c(T) = TumorSolve.apply(p, rho_f, k_f, m, plan); differentiable in
+    p, rho_f and k_f through the library's discrete adjoint."""
+
+    @staticmethod
+    def forward(ctx, p, rho_f, k_f, m, plan: Plan):
+        cT = plan.forward(p.detach(), rho_f.detach(), k_f.detach(), m.detach())
+        ctx.plan = plan
+        ctx.gen = plan.generation
+        ctx.save_for_backward(p.detach(), rho_f.detach(), k_f.detach(), m.detach())
+        return cT.clone()
+
+    @staticmethod
+    def backward(ctx, grad_cT):
+        plan: Plan = ctx.plan
+        if plan.generation != ctx.gen:
+            # another forward used the plan since: rebuild this trajectory
+            p, rho, kf, m = ctx.saved_tensors
+            plan.forward(p, rho, kf, m)
+            ctx.gen = plan.generation
+        gp, gr, gk = plan.vjp(grad_cT.detach())
+        p, rho, kf, _ = ctx.saved_tensors
+        return (gp.view_as(p).to(p.dtype), gr.reshape(rho.shape).to(rho.dtype),
+                gk.reshape(kf.shape).to(kf.dtype), None, None)

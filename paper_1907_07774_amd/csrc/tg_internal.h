@@ -1,0 +1,91 @@
+// Host/device shared definitions of the tumor forward/adjoint library.
+#pragma once
+#include <cstddef>
+#include <cstdint>
+#include <hip/hip_runtime_api.h>
+
+namespace tg {
+
+// Per-problem solver scalars kept in device memory.  Dot products, norms,
+// PCG step lengths and all gradient accumulators are FP64 in both
+// precision modes.
+struct ProbScalars {
+  double rho;       // <r, M r> of the current PCG residual
+  double alpha;     // PCG step length
+  double beta;      // PCG direction update factor
+  double tol2;      // (rtol ||rhs||)^2, grid norm
+  double rr;        // ||r||^2 (grid norm) of the latest residual
+  double rhs2;      // ||rhs||^2 (grid norm) of the current solve
+  double pq;        // <p, q>
+  double kf, rhof;  // k_f and rho_f of this problem
+  double kbar;      // preconditioner coefficient k_f max(m)
+  double mmax;      // max(m)
+  double g_rho, g_k;  // time-integrated gradient accumulators
+  double J;         // misfit
+  double worst;     // worst final relative residual over solves of a call
+  double pad0;
+  int its;          // iterations of the current solve
+  int done;         // current solve finished (converged or failed)
+  int status;       // OR of TG_STAT_* over the solves of a call
+  int first;        // next PCG iteration is the first one
+  int its_total;    // iterations summed over the solves of a call
+  int solves;       // number of solves in the call
+  int its_max;      // largest iteration count of one solve
+  int pad1;
+};
+
+enum : int { STAT_NOT_CONVERGED = 1, STAT_BREAKDOWN = 2, STAT_NONFINITE = 4 };
+
+constexpr int NSLOT = 4;      // simultaneous partial sums per reducing kernel
+constexpr int MAXBLK = 2048;  // max workgroups of a reducing kernel per problem
+
+struct SolverDims {
+  int n, nt, n_p, batch, dirs, s, nseg;
+  double T, sigma, rtol;
+  int maxit;
+};
+
+// Views into the caller-provided workspace.
+struct Workspace {
+  void* spec[8];      // X, R, P, Q, T1, T2, T3, S: [batch][n^3/2] complex
+  void* dspec[8];     // the same set for Hessian directions: [dirs][n^3/2]
+  void* ck;           // [nseg][batch][n^3] checkpoints c^{j s}
+  void* ckb;          // [nseg][batch][n^3] b^{j s - 1} (j >= 1)
+  void* segc;         // [s][batch][n^3]  c^n within the live segment
+  void* segb;         // [s][batch][n^3]  b^n within the live segment
+  void* lam;          // [max(batch, dirs)][n^3] real scratch field
+  double* gfac;       // [batch][n_p][3][n] Gaussian factors
+  double* centres;    // [batch][n_p][3]
+  ProbScalars* sc;    // [batch + dirs]
+  double* part;       // [batch + dirs][NSLOT][MAXBLK]
+  double* partphi;    // [max(batch, dirs)][n_p][phi blocks]
+};
+
+struct CallStats {
+  int solves, its_total, its_max, status;
+  double worst_rel_residual;
+};
+
+class ISolver {
+ public:
+  virtual ~ISolver() {}
+  // forward(p, rho, kf, m) -> c(T); pointers are device pointers with
+  // per-problem strides n_p, 1, 1, n^3, n^3.
+  virtual hipError_t forward(const double* p, const double* rho, const double* kf,
+                             const void* m, void* cT, hipStream_t st) = 0;
+  virtual hipError_t vjp(const void* lamT, const void* cobs, double* J, double* gp,
+                         double* grho, double* gkf, hipStream_t st) = 0;
+  virtual hipError_t hessvec(int ndir, const double* V, double* HV, hipStream_t st) = 0;
+  virtual hipError_t read_stats(CallStats* out, hipStream_t st) = 0;
+  // OR of the PCG status bits the host saw during the last call
+  virtual int last_status() const = 0;
+};
+
+// Phi^T partial-block count for grid size n (workspace sizing).
+int phi_blocks_for(int n);
+ISolver* make_solver_f32(const SolverDims& d, const Workspace& w);
+ISolver* make_solver_f64(const SolverDims& d, const Workspace& w);
+hipError_t init_twiddles_f32();
+hipError_t init_twiddles_f64();
+
+}  // namespace tg

@@ -1,0 +1,1005 @@
+// HIP kernels of the tumor forward/adjoint path (gfx950).
+//
+// Fields.  A real field is [n][n][n] (x slowest, z fastest).  A spectrum is
+// the "packed half spectrum" [kx][ky][kz'] with kz' in [0, n/2): for
+// kz' >= 1 it holds the 3D DFT coefficient at (kx, ky, kz'); slot kz' = 0
+// holds U + i V where U and V are the 2D DFTs of the kz = 0 and kz = n/2
+// planes (both Hermitian).  A spectrum therefore has n^3/2 complex entries,
+// the same bytes as the real field.  Every spectral multiplier used here
+// (derivative symbols with the Nyquist wavenumber zeroed, the Fourier
+// preconditioner) takes the same value on the kz = 0 and kz = n/2 planes,
+// so it acts on slot 0 exactly as on U and V separately, and the grid inner
+// product is sum_k w(kz') Re(conj(a) b) / n^3 with w = 1 on slot 0 and 2
+// elsewhere (the cross terms of U and V cancel over the full plane).
+//
+// Transforms are unnormalized; the 1/n^3 of the inverse is folded into
+// the first inverse pass.  Passes: "x" (stride n^2/2), "y" (stride n/2),
+// "z" (contiguous rows, real <-> packed complex).
+#pragma once
+#include "tg_fft.h"
+#include "tg_internal.h"
+
+namespace tg {
+// Kernels have internal linkage: each precision's translation unit holds
+// its own copy of the shared non-template kernels.
+namespace {
+
+template <typename T> struct Tr;
+template <> struct Tr<float> {
+  static __device__ __forceinline__ float ex(float a) { return __expf(a); }
+};
+template <> struct Tr<double> {
+  static __device__ __forceinline__ double ex(double a) { return exp(a); }
+};
+
+// Derivative symbol of a full axis, Nyquist zeroed.
+template <int N>
+__device__ __forceinline__ int wfull(int k) { return k < N / 2 ? k : (k == N / 2 ? 0 : k - N); }
+
+// ------------------------------------------------------------- reaction
+// Exact logistic flow over tau, R(u) = u E / (1 + u (E - 1)), E = exp(rho tau),
+// rho = rho_f m (Sec. 2.1 reaction term, Sec. 3.3 analytic step).
+template <typename T>
+__device__ __forceinline__ T react(T u, T E) { return u * E / (T(1) + u * (E - T(1))); }
+template <typename T>
+__device__ __forceinline__ T react_du(T u, T E) {
+  T D = T(1) + u * (E - T(1));
+  return E / (D * D);
+}
+
+// ------------------------------------------------------------ reductions
+template <int NT>
+__device__ __forceinline__ void block_sums(double (&v)[NSLOT], int ns, double* red) {
+  // deterministic: fixed xor-shuffle tree inside each wave, then waves in
+  // order on thread 0.  red needs NSLOT * NT/64 doubles.
+  constexpr int NW = (NT + 63) / 64;
+  constexpr int WW = NT < 64 ? NT : 64;  // active lanes of a wave
+  for (int s = 0; s < ns; ++s) {
+    double x = v[s];
+#pragma unroll
+    for (int o = WW / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, WW);
+    v[s] = x;
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0)
+    for (int s = 0; s < ns; ++s) red[s * NW + wid] = v[s];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int s = 0; s < ns; ++s) {
+      double acc = 0.0;
+      for (int w = 0; w < NW; ++w) acc += red[s * NW + w];
+      v[s] = acc;
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ double* part_at(double* part, int b, int s) {
+  return part + ((size_t)b * NSLOT + s) * MAXBLK;
+}
+
+// ------------------------------------------------------ strided passes
+// Pass along x (AX = 0) or y (AX = 1) of a packed spectrum.  Column index
+// gc enumerates the n * n/2 pencils: for x, gc = ky * n/2 + kz'; for y,
+// gc = x * n/2 + kz'.  A workgroup takes C consecutive pencils; thread
+// (col, t) holds positions t + TT e of pencil col.
+template <typename T, int N, int C, int AX>
+struct SP {
+  static constexpr int NH = N / 2;
+  static constexpr int L = N;
+  static constexpr int E = FftE<N>::value;
+  static constexpr int TT = L / E;
+  static constexpr int NT = C * TT;
+  static constexpr int NCOL = N * NH;
+  static constexpr int NBLK = NCOL / C;
+  static constexpr long long PSTR = AX == 0 ? (long long)N * NH : NH;
+  static constexpr long long SPEC = (long long)N * N * NH;  // complex per problem
+  static __device__ __forceinline__ long long colbase(int gc) {
+    return AX == 0 ? (long long)gc : (long long)(gc / NH) * (N * NH) + (gc % NH);
+  }
+};
+
+#define SP_SETUP(AXV)                                                   \
+  using S = SP<T, N, C, AXV>;                                           \
+  constexpr int E = S::E, TT = S::TT, NH = S::NH;                       \
+  (void)NH;                                                             \
+  __shared__ cx<T> lds[(S::TT > 1) ? N * C : 1];                        \
+  const int b = blockIdx.y;                                             \
+  const int col = threadIdx.x % C, t = threadIdx.x / C;                 \
+  const int gc = blockIdx.x * C + col;                                  \
+  const long long base = (long long)b * S::SPEC + S::colbase(gc);
+
+// ---- x pass, inverse, gradient prologue of the diffusion matvec.
+// MODE 0: p is given.  MODE 1: PCG direction p = M r + beta p (stored).
+// Out: U1 = IFFT_x(s i wx p), U2 = IFFT_x(s p), s = 1/n^3.
+template <typename T, int N, int C, int MODE>
+__global__ void __launch_bounds__((SP<T, N, C, 0>::NT))
+k_x_inv_grad(cx<T>* __restrict__ P, const cx<T>* __restrict__ Rr, cx<T>* __restrict__ U1,
+             cx<T>* __restrict__ U2, const ProbScalars* __restrict__ sc, double tau, int pred) {
+  SP_SETUP(0)
+  if (pred && sc[b].done) return;
+  const int ky = gc / NH, kz = gc % NH;
+  const T wy = (T)wfull<N>(ky), wz = (T)kz;
+  const T s = T(1) / (T(N) * T(N) * T(N));
+  cx<T> v[E], w[E];
+  if constexpr (MODE == 1) {
+    const bool first = sc[b].first != 0;
+    const T beta = (T)sc[b].beta;
+    const T kb = (T)(tau * sc[b].kbar);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int kx = t + TT * e;
+      const T wx = (T)wfull<N>(kx);
+      const T pre = T(1) / (T(1) + kb * (wx * wx + wy * wy + wz * wz));
+      const long long o = base + kx * S::PSTR;
+      cx<T> p = scale(Rr[o], pre);
+      if (!first) p = p + scale(P[o], beta);
+      P[o] = p;
+      v[e] = p;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = P[base + (t + TT * e) * S::PSTR];
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const T wx = (T)wfull<N>(t + TT * e);
+    w[e] = mul_i(v[e], s * wx);
+    v[e] = scale(v[e], s);
+  }
+  fft<T, N, E, true, C, 1>(w, lds, t, col);
+#pragma unroll
+  for (int e = 0; e < E; ++e) U1[base + (t + TT * e) * S::PSTR] = w[e];
+  fft<T, N, E, true, C, 1>(v, lds, t, col);
+#pragma unroll
+  for (int e = 0; e < E; ++e) U2[base + (t + TT * e) * S::PSTR] = v[e];
+}
+
+// ---- y pass, inverse: V1 = IFFT_y(U1) (in place), V2 = IFFT_y(i wy U2)
+// (in place), V3 = IFFT_y(U2).
+template <typename T, int N, int C>
+__global__ void __launch_bounds__((SP<T, N, C, 1>::NT))
+k_y_inv_grad(cx<T>* __restrict__ U1, cx<T>* __restrict__ U2, cx<T>* __restrict__ V3,
+             const ProbScalars* __restrict__ sc, int pred) {
+  SP_SETUP(1)
+  if (pred && sc[b].done) return;
+  cx<T> v[E], w[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = U1[base + (t + TT * e) * S::PSTR];
+  fft<T, N, E, true, C, 1>(v, lds, t, col);
+#pragma unroll
+  for (int e = 0; e < E; ++e) U1[base + (t + TT * e) * S::PSTR] = v[e];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    v[e] = U2[base + (t + TT * e) * S::PSTR];
+    w[e] = mul_i(v[e], (T)wfull<N>(t + TT * e));
+  }
+  fft<T, N, E, true, C, 1>(v, lds, t, col);
+#pragma unroll
+  for (int e = 0; e < E; ++e) V3[base + (t + TT * e) * S::PSTR] = v[e];
+  fft<T, N, E, true, C, 1>(w, lds, t, col);
+#pragma unroll
+  for (int e = 0; e < E; ++e) U2[base + (t + TT * e) * S::PSTR] = w[e];
+}
+
+// ---- y pass, forward: W1 = FFT_y(H1) (in place), W23 = i wy FFT_y(H2) +
+// FFT_y(H3) (into H2).
+template <typename T, int N, int C>
+__global__ void __launch_bounds__((SP<T, N, C, 1>::NT))
+k_y_fwd_div(cx<T>* __restrict__ H1, cx<T>* __restrict__ H2, const cx<T>* __restrict__ H3,
+            const ProbScalars* __restrict__ sc, int pred) {
+  SP_SETUP(1)
+  if (pred && sc[b].done) return;
+  cx<T> v[E], w[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = H1[base + (t + TT * e) * S::PSTR];
+  fft<T, N, E, false, C, 1>(v, lds, t, col);
+#pragma unroll
+  for (int e = 0; e < E; ++e) H1[base + (t + TT * e) * S::PSTR] = v[e];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = H2[base + (t + TT * e) * S::PSTR];
+  fft<T, N, E, false, C, 1>(v, lds, t, col);
+#pragma unroll
+  for (int e = 0; e < E; ++e) w[e] = H3[base + (t + TT * e) * S::PSTR];
+  fft<T, N, E, false, C, 1>(w, lds, t, col);
+#pragma unroll
+  for (int e = 0; e < E; ++e)
+    H2[base + (t + TT * e) * S::PSTR] = mul_i(v[e], (T)wfull<N>(t + TT * e)) + w[e];
+}
+
+// ---- x pass, forward, divergence epilogue of the diffusion matvec:
+// Am = i wx FFT_x(W1) + FFT_x(W23) is the spectrum of div(m grad u).
+enum XMode : int {
+  XM_PCG = 0,      // q = p - tau kf Am; partial <p, q>
+  XM_RHS_FWD = 1,  // x0 = X; r = 2 tau kf Am; partials |rhs|^2, <r, M r>, |r|^2
+  XM_RHS_ADJ = 2,  // x0 = X; r = tau kf Am;  rhs = X
+  XM_POST_ADJ = 3  // X += tau kf Am; partial <Am, S> (k_f gradient)
+};
+
+template <typename T, int N, int C, int MODE>
+__global__ void __launch_bounds__((SP<T, N, C, 0>::NT))
+k_x_fwd_div(const cx<T>* __restrict__ W1, const cx<T>* __restrict__ W23, cx<T>* __restrict__ X,
+            cx<T>* __restrict__ Q, const cx<T>* __restrict__ Sv, const ProbScalars* __restrict__ sc,
+            double* __restrict__ part, double tau, int pred, int want_gk) {
+  SP_SETUP(0)
+  __shared__ double red[NSLOT * ((S::NT + 63) / 64)];
+  if (pred && sc[b].done) return;
+  const int ky = gc / NH, kz = gc % NH;
+  const T wy = (T)wfull<N>(ky), wz = (T)kz;
+  const double wgt = kz == 0 ? 1.0 : 2.0;
+  cx<T> a[E], c[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) a[e] = W1[base + (t + TT * e) * S::PSTR];
+  fft<T, N, E, false, C, 1>(a, lds, t, col);
+#pragma unroll
+  for (int e = 0; e < E; ++e) c[e] = W23[base + (t + TT * e) * S::PSTR];
+  fft<T, N, E, false, C, 1>(c, lds, t, col);
+  const T tk = (T)(tau * sc[b].kf);
+  double acc[NSLOT] = {0.0, 0.0, 0.0, 0.0};
+  int ns = 0;
+  if constexpr (MODE == XM_PCG) {
+    ns = 1;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int kx = t + TT * e;
+      const long long o = base + kx * S::PSTR;
+      const cx<T> am = mul_i(a[e], (T)wfull<N>(kx)) + c[e];
+      const cx<T> p = X[o];
+      const cx<T> q = p - scale(am, tk);
+      Q[o] = q;
+      acc[0] += wgt * ((double)p.x * (double)q.x + (double)p.y * (double)q.y);
+    }
+  } else if constexpr (MODE == XM_RHS_FWD || MODE == XM_RHS_ADJ) {
+    ns = 3;
+    const T kb = (T)(tau * sc[b].kbar);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int kx = t + TT * e;
+      const long long o = base + kx * S::PSTR;
+      const T wx = (T)wfull<N>(kx);
+      const cx<T> am = mul_i(a[e], wx) + c[e];
+      const cx<T> x0 = X[o];
+      cx<T> r, rhs;
+      if constexpr (MODE == XM_RHS_FWD) {
+        r = scale(am, T(2) * tk);
+        rhs = x0 + scale(am, tk);
+      } else {
+        r = scale(am, tk);
+        rhs = x0;
+      }
+      Q[o] = r;
+      const T pre = T(1) / (T(1) + kb * (wx * wx + wy * wy + wz * wz));
+      const double rr = (double)r.x * (double)r.x + (double)r.y * (double)r.y;
+      acc[0] += wgt * ((double)rhs.x * (double)rhs.x + (double)rhs.y * (double)rhs.y);
+      acc[1] += wgt * (double)pre * rr;
+      acc[2] += wgt * rr;
+    }
+  } else {
+    ns = 1;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int kx = t + TT * e;
+      const long long o = base + kx * S::PSTR;
+      const cx<T> am = mul_i(a[e], (T)wfull<N>(kx)) + c[e];
+      if (want_gk) {
+        const cx<T> sv = Sv[o];
+        acc[0] += wgt * ((double)am.x * (double)sv.x + (double)am.y * (double)sv.y);
+      }
+      X[o] = X[o] + scale(am, tk);
+    }
+  }
+  block_sums<S::NT>(acc, ns, red);
+  if (threadIdx.x == 0)
+    for (int s2 = 0; s2 < ns; ++s2) part_at(part, b, s2)[blockIdx.x] = acc[s2];
+}
+
+// ---- plain passes of a single spectrum (state transforms).
+// x inverse with 1/n^3 scaling: Y = IFFT_x(X / n^3)
+template <typename T, int N, int C>
+__global__ void __launch_bounds__((SP<T, N, C, 0>::NT))
+k_x_inv(const cx<T>* __restrict__ X, cx<T>* __restrict__ Y) {
+  SP_SETUP(0)
+  const T s = T(1) / (T(N) * T(N) * T(N));
+  cx<T> v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = scale(X[base + (t + TT * e) * S::PSTR], s);
+  fft<T, N, E, true, C, 1>(v, lds, t, col);
+#pragma unroll
+  for (int e = 0; e < E; ++e) Y[base + (t + TT * e) * S::PSTR] = v[e];
+}
+
+// y pass in place, forward or inverse, on one or two spectra.
+template <typename T, int N, int C, bool INV>
+__global__ void __launch_bounds__((SP<T, N, C, 1>::NT))
+k_y_plain(cx<T>* __restrict__ Y, cx<T>* __restrict__ Y2) {
+  SP_SETUP(1)
+  cx<T> v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = Y[base + (t + TT * e) * S::PSTR];
+  fft<T, N, E, INV, C, 1>(v, lds, t, col);
+#pragma unroll
+  for (int e = 0; e < E; ++e) Y[base + (t + TT * e) * S::PSTR] = v[e];
+  if (Y2 != nullptr) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = Y2[base + (t + TT * e) * S::PSTR];
+    fft<T, N, E, INV, C, 1>(v, lds, t, col);
+#pragma unroll
+    for (int e = 0; e < E; ++e) Y2[base + (t + TT * e) * S::PSTR] = v[e];
+  }
+}
+
+// x pass forward of the state spectrum H -> X, optionally followed in the
+// same kernel by the gradient prologue of the matvec on X (U1, U2), and
+// optionally a plain forward x pass of a second spectrum S2 (in place).
+template <typename T, int N, int C>
+__global__ void __launch_bounds__((SP<T, N, C, 0>::NT))
+k_x_fwd_state(const cx<T>* __restrict__ H, cx<T>* __restrict__ X, cx<T>* __restrict__ U1,
+              cx<T>* __restrict__ U2, cx<T>* __restrict__ S2) {
+  SP_SETUP(0)
+  cx<T> v[E], w[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = H[base + (t + TT * e) * S::PSTR];
+  fft<T, N, E, false, C, 1>(v, lds, t, col);
+#pragma unroll
+  for (int e = 0; e < E; ++e) X[base + (t + TT * e) * S::PSTR] = v[e];
+  if (U1 != nullptr) {
+    const T s = T(1) / (T(N) * T(N) * T(N));
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const T wx = (T)wfull<N>(t + TT * e);
+      w[e] = mul_i(v[e], s * wx);
+      v[e] = scale(v[e], s);
+    }
+    fft<T, N, E, true, C, 1>(w, lds, t, col);
+#pragma unroll
+    for (int e = 0; e < E; ++e) U1[base + (t + TT * e) * S::PSTR] = w[e];
+    fft<T, N, E, true, C, 1>(v, lds, t, col);
+#pragma unroll
+    for (int e = 0; e < E; ++e) U2[base + (t + TT * e) * S::PSTR] = v[e];
+  }
+  if (S2 != nullptr) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = S2[base + (t + TT * e) * S::PSTR];
+    fft<T, N, E, false, C, 1>(v, lds, t, col);
+#pragma unroll
+    for (int e = 0; e < E; ++e) S2[base + (t + TT * e) * S::PSTR] = v[e];
+  }
+}
+
+// ------------------------------------------------------------- z passes
+// Rows (b, x, y) of n reals = n/2 complex.  RW rows per workgroup; thread
+// (t, row) holds complex positions t + TT e.  LDS row pitch L + TT spreads
+// the rows of a wave over the banks.
+template <typename T, int N>
+struct ZP {
+  static constexpr int L = N / 2;
+  static constexpr int E = FftE<L>::value;
+  static constexpr int TT = L / E;
+  static constexpr int RW = (TT * 64 <= 256) ? 64 : 256 / TT;
+  static constexpr int NT = TT * RW;
+  static constexpr int PITCH = L + TT;
+  static constexpr int NBLK = N * N / RW;
+  static constexpr long long SPEC = (long long)N * N * (N / 2);
+  static constexpr long long REAL = (long long)N * N * N;
+};
+
+// Unnormalized C2R of one packed row: in v[e] = Y[k], k = t + TT e;
+// out v[e] = n (x[2j] + i x[2j+1]), j = t + TT e.
+template <typename T, int N, int E>
+__device__ __forceinline__ void c2r_row(cx<T> (&v)[E], cx<T>* lds, int t, int row) {
+  using Z = ZP<T, N>;
+  static_assert(E == Z::E, "row register count");
+  constexpr int L = Z::L, TT = Z::TT;
+  cx<T>* lr = lds + row * Z::PITCH;
+#pragma unroll
+  for (int e = 0; e < E; ++e) lr[t + TT * e] = v[e];
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int k = t + TT * e;
+    const cx<T> xk = v[e];
+    if (k == 0) {
+      // X0 = Re Y0, X_{n/2} = Im Y0
+      v[e] = mk(xk.x + xk.y, xk.x - xk.y);
+    } else {
+      const cx<T> xm = conjg(lr[L - k]);
+      const cx<T> sum = xk + xm, dif = xk - xm;
+      // i W_n^{-k} dif, W_n^{-k} = conj(tw)
+      const cx<T> wk = conjg(twiddle<T, false, N>(k));
+      const cx<T> tdif = cmul(wk, dif);
+      v[e] = sum + mk(-tdif.y, tdif.x);
+    }
+  }
+  __syncthreads();
+  fft<T, L, E, true, 1, Z::PITCH>(v, lds, t, row);
+}
+
+// Unnormalized R2C of one row: in v[e] = x[2j] + i x[2j+1]; out v[e] =
+// packed Y[k] (slot 0 = X0 + i X_{n/2}).
+template <typename T, int N, int E>
+__device__ __forceinline__ void r2c_row(cx<T> (&v)[E], cx<T>* lds, int t, int row) {
+  using Z = ZP<T, N>;
+  static_assert(E == Z::E, "row register count");
+  constexpr int L = Z::L, TT = Z::TT;
+  fft<T, L, E, false, 1, Z::PITCH>(v, lds, t, row);
+  cx<T>* lr = lds + row * Z::PITCH;
+#pragma unroll
+  for (int e = 0; e < E; ++e) lr[t + TT * e] = v[e];
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int k = t + TT * e;
+    const cx<T> zk = v[e];
+    if (k == 0) {
+      v[e] = mk(zk.x + zk.y, zk.x - zk.y);
+    } else {
+      const cx<T> zm = conjg(lr[L - k]);
+      const cx<T> sum = zk + zm, dif = zk - zm;
+      // X = (sum - i W^k dif) / 2
+      const cx<T> td = cmul(twiddle<T, false, N>(k), dif);
+      v[e] = scale(sum + mk(td.y, -td.x), T(0.5));
+    }
+  }
+  __syncthreads();
+}
+
+#define ZP_SETUP                                                        \
+  using Z = ZP<T, N>;                                                   \
+  constexpr int E = Z::E, TT = Z::TT;                                   \
+  __shared__ cx<T> lds[Z::RW * Z::PITCH];                               \
+  const int b = blockIdx.y;                                             \
+  const int t = threadIdx.x % TT, row = threadIdx.x / TT;               \
+  const long long grow = (long long)blockIdx.x * Z::RW + row;           \
+  const long long sbase = (long long)b * Z::SPEC + grow * Z::L;         \
+  (void)sbase;
+
+// ---- matvec core: for j = x, y, z: g_j = C2R(V_j) (V_z times i wz), times
+// m, R2C, (z: times i wz).  In place on V1..V3.
+template <typename T, int N>
+__global__ void __launch_bounds__((ZP<T, N>::NT))
+k_z_matvec(cx<T>* __restrict__ V1, cx<T>* __restrict__ V2, cx<T>* __restrict__ V3,
+           const T* __restrict__ m, long long m_bs, const ProbScalars* __restrict__ sc, int pred) {
+  ZP_SETUP
+  if (pred && sc[b].done) return;
+  const cx<T>* mrow = reinterpret_cast<const cx<T>*>(m + b * m_bs + grow * N);
+  cx<T> mv[E], v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) mv[e] = mrow[t + TT * e];
+  cx<T>* Vs[3] = {V1, V2, V3};
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    cx<T>* V = Vs[j] + sbase;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      v[e] = V[t + TT * e];
+      if (j == 2) v[e] = mul_i(v[e], (T)(t + TT * e));
+    }
+    c2r_row<T, N>(v, lds, t, row);
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = mk(v[e].x * mv[e].x, v[e].y * mv[e].y);
+    r2c_row<T, N>(v, lds, t, row);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if (j == 2) v[e] = mul_i(v[e], (T)(t + TT * e));
+      V[t + TT * e] = v[e];
+    }
+  }
+}
+
+// ---- time-step boundary kernels (reaction halves fused around the
+// transforms).  Real fields: Cin (input real field), Cst/Bst (stored
+// states), m.  Spectral rows: Xs (in and/or out), Y2 (second output).
+enum ZMode : int {
+  ZS_FWD_FIRST = 0,  // a = R(c0) -> R2C
+  ZS_FWD = 1,        // b = C2R; [store b]; c = R(b); [store c]; a = R(c) -> R2C
+  ZS_FWD_LAST = 2,   // b = C2R; [store b]; c = R(b) -> store c (to Cst)
+  ZS_TAN_FIRST = 3,  // a' = R'(c0) dc0 -> R2C           (Cin = dc0, Cst = c0)
+  ZS_TAN = 4,        // b' = C2R; c' = R'(b) b'; a' = R'(R(b)) c' -> R2C  (Bst = b)
+  ZS_TAN_LAST = 5,   // b' = C2R; c' = R'(b) b' -> store c' (Cout)
+  ZS_ADJ_FIRST = 6,  // lam = Cin; head of last step -> R2C(lam), R2C(a + b)
+  ZS_ADJ = 7,        // lam = C2R; tail of step n+1, head of step n -> R2C x2
+  ZS_ADJ_LAST = 8    // lam = C2R; tail of step 0 -> store lam (Cout)
+};
+
+struct ZArgs {
+  const void* Cin; long long cin_bs;   // real input field
+  const void* Cn; long long cn_bs;     // c^n (adjoint, tangent first)
+  const void* Bn; long long bn_bs;     // b^n (adjoint) / b^{n-1} (tangent)
+  void* Bst; long long bst_bs;         // store b here (forward)
+  void* Cst; long long cst_bs;         // store c here (forward) / output
+  const void* m; long long m_bs;
+  void* Xs;                            // spectral rows in/out
+  void* Y2;                            // second spectral output (adjoint)
+  ProbScalars* sc;
+  double* part;
+  double tau;
+  double out_scale;                    // factor on the stored tangent output
+  int want_grho;
+};
+
+template <typename T, int N, int MODE>
+__global__ void __launch_bounds__((ZP<T, N>::NT)) k_z_step(ZArgs a) {
+  ZP_SETUP
+  __shared__ double red[NSLOT * ((Z::NT + 63) / 64)];
+  const long long roff = grow * N;  // real element offset of the row
+  const T tau = (T)a.tau;
+  const T rhof = (T)a.sc[b].rhof;
+  const cx<T>* mrow = reinterpret_cast<const cx<T>*>((const T*)a.m + b * a.m_bs + roff);
+  cx<T> mv[E], E2[E], v[E];
+  // E = exp(rho_f m tau) for both reals of each complex slot
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    mv[e] = mrow[t + TT * e];
+    E2[e] = mk(Tr<T>::ex(rhof * mv[e].x * tau), Tr<T>::ex(rhof * mv[e].y * tau));
+  }
+  cx<T>* X = reinterpret_cast<cx<T>*>(a.Xs) + sbase;
+  auto ldreal = [&](const void* p, long long bs, cx<T> (&o)[E]) {
+    const cx<T>* r = reinterpret_cast<const cx<T>*>((const T*)p + b * bs + roff);
+#pragma unroll
+    for (int e = 0; e < E; ++e) o[e] = r[t + TT * e];
+  };
+  auto streal = [&](void* p, long long bs, const cx<T> (&o)[E]) {
+    cx<T>* r = reinterpret_cast<cx<T>*>((T*)p + b * bs + roff);
+#pragma unroll
+    for (int e = 0; e < E; ++e) r[t + TT * e] = o[e];
+  };
+  double gr = 0.0;
+  // d rho contribution <lam, m tau u (1 - u)> for one pair
+  auto drho = [&](cx<T> lam, cx<T> u, cx<T> mm) -> double {
+    return (double)lam.x * (double)(mm.x * tau * u.x * (T(1) - u.x)) +
+           (double)lam.y * (double)(mm.y * tau * u.y * (T(1) - u.y));
+  };
+  if constexpr (MODE == ZS_FWD_FIRST) {
+    ldreal(a.Cin, a.cin_bs, v);
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = mk(react(v[e].x, E2[e].x), react(v[e].y, E2[e].y));
+    r2c_row<T, N>(v, lds, t, row);
+#pragma unroll
+    for (int e = 0; e < E; ++e) X[t + TT * e] = v[e];
+  } else if constexpr (MODE == ZS_FWD || MODE == ZS_FWD_LAST) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = X[t + TT * e];
+    c2r_row<T, N>(v, lds, t, row);
+    if (a.Bst) streal(a.Bst, a.bst_bs, v);
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = mk(react(v[e].x, E2[e].x), react(v[e].y, E2[e].y));
+    if (a.Cst) streal(a.Cst, a.cst_bs, v);
+    if constexpr (MODE == ZS_FWD) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = mk(react(v[e].x, E2[e].x), react(v[e].y, E2[e].y));
+      r2c_row<T, N>(v, lds, t, row);
+#pragma unroll
+      for (int e = 0; e < E; ++e) X[t + TT * e] = v[e];
+    }
+  } else if constexpr (MODE == ZS_TAN_FIRST) {
+    cx<T> c0[E];
+    ldreal(a.Cin, a.cin_bs, v);
+    ldreal(a.Cn, a.cn_bs, c0);
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      v[e] = mk(react_du(c0[e].x, E2[e].x) * v[e].x, react_du(c0[e].y, E2[e].y) * v[e].y);
+    r2c_row<T, N>(v, lds, t, row);
+#pragma unroll
+    for (int e = 0; e < E; ++e) X[t + TT * e] = v[e];
+  } else if constexpr (MODE == ZS_TAN || MODE == ZS_TAN_LAST) {
+    cx<T> bb[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = X[t + TT * e];
+    c2r_row<T, N>(v, lds, t, row);
+    ldreal(a.Bn, a.bn_bs, bb);
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      v[e] = mk(react_du(bb[e].x, E2[e].x) * v[e].x, react_du(bb[e].y, E2[e].y) * v[e].y);
+    if constexpr (MODE == ZS_TAN) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const cx<T> c = mk(react(bb[e].x, E2[e].x), react(bb[e].y, E2[e].y));
+        v[e] = mk(react_du(c.x, E2[e].x) * v[e].x, react_du(c.y, E2[e].y) * v[e].y);
+      }
+      r2c_row<T, N>(v, lds, t, row);
+#pragma unroll
+      for (int e = 0; e < E; ++e) X[t + TT * e] = v[e];
+    } else {
+      const T os = (T)a.out_scale;
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = scale(v[e], os);
+      streal(a.Cst, a.cst_bs, v);
+    }
+  } else {
+    // adjoint modes
+    cx<T> bb[E], cc[E];
+    if constexpr (MODE == ZS_ADJ_FIRST) {
+      ldreal(a.Cin, a.cin_bs, v);
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = X[t + TT * e];
+      c2r_row<T, N>(v, lds, t, row);
+    }
+    if constexpr (MODE == ZS_ADJ) {
+      // tail of step n+1: c1 = R(b^n), a1 = R(c1)
+      ldreal(a.Bn, a.bn_bs, bb);
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const cx<T> c1 = mk(react(bb[e].x, E2[e].x), react(bb[e].y, E2[e].y));
+        const cx<T> a1 = mk(react(c1.x, E2[e].x), react(c1.y, E2[e].y));
+        gr += drho(v[e], a1, mv[e]);
+        v[e] = mk(react_du(c1.x, E2[e].x) * v[e].x, react_du(c1.y, E2[e].y) * v[e].y);
+      }
+    }
+    if constexpr (MODE == ZS_ADJ_FIRST) ldreal(a.Bn, a.bn_bs, bb);
+    if constexpr (MODE == ZS_ADJ_LAST) {
+      ldreal(a.Cn, a.cn_bs, cc);
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const cx<T> a0 = mk(react(cc[e].x, E2[e].x), react(cc[e].y, E2[e].y));
+        gr += drho(v[e], a0, mv[e]);
+        v[e] = mk(react_du(cc[e].x, E2[e].x) * v[e].x, react_du(cc[e].y, E2[e].y) * v[e].y);
+      }
+      streal(a.Cst, a.cst_bs, v);
+    } else {
+      // head of step n: c1 = R(b^n): g += <lam, m tau c1 (1 - c1)>; lam *= R'(b^n)
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const cx<T> c1 = mk(react(bb[e].x, E2[e].x), react(bb[e].y, E2[e].y));
+        gr += drho(v[e], c1, mv[e]);
+        v[e] = mk(react_du(bb[e].x, E2[e].x) * v[e].x, react_du(bb[e].y, E2[e].y) * v[e].y);
+      }
+      r2c_row<T, N>(v, lds, t, row);
+#pragma unroll
+      for (int e = 0; e < E; ++e) X[t + TT * e] = v[e];
+      // s = a^n + b^n, a^n = R(c^n)
+      ldreal(a.Cn, a.cn_bs, cc);
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        v[e] = mk(react(cc[e].x, E2[e].x) + bb[e].x, react(cc[e].y, E2[e].y) + bb[e].y);
+      r2c_row<T, N>(v, lds, t, row);
+      cx<T>* Y2 = reinterpret_cast<cx<T>*>(a.Y2) + sbase;
+#pragma unroll
+      for (int e = 0; e < E; ++e) Y2[t + TT * e] = v[e];
+    }
+    if (a.want_grho) {
+      double acc[NSLOT] = {gr, 0.0, 0.0, 0.0};
+      block_sums<Z::NT>(acc, 1, red);
+      if (threadIdx.x == 0) part_at(a.part, b, 0)[blockIdx.x] = acc[0];
+    }
+  }
+}
+
+// --------------------------------------------------- pointwise spectral
+template <typename T, int N>
+struct PW {
+  static constexpr int NT = 256;
+  static constexpr long long SPEC = (long long)N * N * (N / 2);
+  static constexpr int NBLK = (SPEC / NT / 8) < 1024 ? (int)((SPEC / NT / 8) > 0 ? SPEC / NT / 8 : 1) : 1024;
+};
+
+// x += alpha p; r -= alpha q; partials <r, M r>, |r|^2.
+template <typename T, int N>
+__global__ void __launch_bounds__(256)
+k_pcg_update(cx<T>* __restrict__ X, cx<T>* __restrict__ R, const cx<T>* __restrict__ P,
+             const cx<T>* __restrict__ Q, const ProbScalars* __restrict__ sc,
+             double* __restrict__ part, double tau) {
+  using W = PW<T, N>;
+  __shared__ double red[NSLOT * 4];
+  const int b = blockIdx.y;
+  if (sc[b].done) return;
+  constexpr int NH = N / 2;
+  const T al = (T)sc[b].alpha;
+  const T kb = (T)(tau * sc[b].kbar);
+  const long long off = (long long)b * W::SPEC;
+  double acc[NSLOT] = {0.0, 0.0, 0.0, 0.0};
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < W::SPEC;
+       i += (long long)gridDim.x * 256) {
+    const int kz = (int)(i % NH);
+    const int ky = (int)((i / NH) % N);
+    const int kx = (int)(i / ((long long)NH * N));
+    const T wx = (T)wfull<N>(kx), wy = (T)wfull<N>(ky), wz = (T)kz;
+    const T pre = T(1) / (T(1) + kb * (wx * wx + wy * wy + wz * wz));
+    const double wgt = kz == 0 ? 1.0 : 2.0;
+    const long long o = off + i;
+    X[o] = X[o] + scale(P[o], al);
+    const cx<T> r = R[o] - scale(Q[o], al);
+    R[o] = r;
+    const double rr = (double)r.x * (double)r.x + (double)r.y * (double)r.y;
+    acc[0] += wgt * (double)pre * rr;
+    acc[1] += wgt * rr;
+  }
+  block_sums<256>(acc, 2, red);
+  if (threadIdx.x == 0) {
+    part_at(part, b, 0)[blockIdx.x] = acc[0];
+    part_at(part, b, 1)[blockIdx.x] = acc[1];
+  }
+}
+
+// ---------------------------------------------------------- finalizers
+enum FinMode : int {
+  FIN_INIT = 0,   // slots: |rhs|^2, <r,Mr>, |r|^2
+  FIN_PQ = 1,     // slot: <p,q>
+  FIN_RZ = 2,     // slots: <r,Mr>, |r|^2
+  FIN_GRHO = 3,   // slot: g_rho increment
+  FIN_GK = 4,     // slot: spectral <Am mu, s>
+  FIN_J = 5,      // slot: sum (c - d)^2
+  FIN_MMAX = 6    // slot: partial max(m)
+};
+
+template <int MODE>
+__global__ void __launch_bounds__(256)
+k_finalize(ProbScalars* __restrict__ sc, const double* __restrict__ part, int nblk,
+           double scale_, double rtol, int maxit) {
+  __shared__ double red[NSLOT * 4];
+  const int b = blockIdx.x;
+  ProbScalars& S = sc[b];
+  if ((MODE == FIN_PQ || MODE == FIN_RZ) && S.done) return;
+  constexpr int ns = MODE == FIN_INIT ? 3 : MODE == FIN_RZ ? 2 : 1;
+  double acc[NSLOT] = {0.0, 0.0, 0.0, 0.0};
+  if constexpr (MODE == FIN_MMAX) {
+    double mx = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += 256) mx = fmax(mx, part_at((double*)part, b, 0)[i]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+      S.mmax = mx;
+      S.kbar = S.kf * mx;
+    }
+    return;
+  }
+  for (int s = 0; s < ns; ++s)
+    for (int i = threadIdx.x; i < nblk; i += 256) acc[s] += part_at((double*)part, b, s)[i];
+  block_sums<256>(acc, ns, red);
+  if (threadIdx.x != 0) return;
+  if constexpr (MODE == FIN_INIT) {
+    S.rhs2 = acc[0] * scale_;
+    S.rho = acc[1];
+    S.rr = acc[2] * scale_;
+    S.tol2 = rtol * rtol * S.rhs2;
+    S.its = 0;
+    S.first = 1;
+    S.solves += 1;
+    S.done = (S.rr <= S.tol2) ? 1 : 0;
+    if (!isfinite(S.rr) || !isfinite(S.rhs2)) {
+      S.status |= STAT_NONFINITE;
+      S.done = 1;
+    }
+    if (S.done) {
+      const double rel = S.rhs2 > 0 ? sqrt(S.rr / S.rhs2) : 0.0;
+      S.worst = fmax(S.worst, rel);
+    }
+  } else if constexpr (MODE == FIN_PQ) {
+    S.pq = acc[0];
+    if (!(acc[0] > 0.0) || !isfinite(acc[0])) {
+      S.status |= isfinite(acc[0]) ? STAT_BREAKDOWN : STAT_NONFINITE;
+      S.done = 1;
+      S.alpha = 0.0;
+      const double rel = S.rhs2 > 0 ? sqrt(S.rr / S.rhs2) : 0.0;
+      S.worst = fmax(S.worst, rel);
+    } else {
+      S.alpha = S.rho / acc[0];
+    }
+  } else if constexpr (MODE == FIN_RZ) {
+    const double rho_new = acc[0];
+    S.rr = acc[1] * scale_;
+    S.its += 1;
+    S.its_total += 1;
+    if (S.its > S.its_max) S.its_max = S.its;
+    S.beta = rho_new / S.rho;
+    S.rho = rho_new;
+    S.first = 0;
+    bool fin = false;
+    if (!isfinite(S.rr)) {
+      S.status |= STAT_NONFINITE;
+      fin = true;
+    } else if (S.rr <= S.tol2) {
+      fin = true;
+    } else if (S.its >= maxit) {
+      S.status |= STAT_NOT_CONVERGED;
+      fin = true;
+    }
+    if (fin) {
+      S.done = 1;
+      const double rel = S.rhs2 > 0 ? sqrt(S.rr / S.rhs2) : 0.0;
+      S.worst = fmax(S.worst, rel);
+    }
+  } else if constexpr (MODE == FIN_GRHO) {
+    S.g_rho += acc[0] * scale_;
+  } else if constexpr (MODE == FIN_GK) {
+    S.g_k += acc[0] * scale_;
+  } else if constexpr (MODE == FIN_J) {
+    S.J = acc[0] * scale_;
+  }
+}
+
+// Copy the done flags of all problems to a host-visible array.
+__global__ void k_done_flags(const ProbScalars* __restrict__ sc, int* __restrict__ out, int nb) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nb) out[i] = sc[i].done;
+}
+
+// Reset per-call scalars and load parameters.
+__global__ void k_init_scalars(ProbScalars* __restrict__ sc, const double* __restrict__ rho,
+                               long long rho_bs, const double* __restrict__ kf, long long kf_bs,
+                               int nb) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  ProbScalars S{};
+  S.rhof = rho[b * rho_bs];
+  S.kf = kf[b * kf_bs];
+  S.done = 1;
+  sc[b] = S;
+}
+
+// Reset the per-call accumulators only (keep kf, rho, kbar, mmax).
+__global__ void k_reset_call(ProbScalars* __restrict__ sc, int nb) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  ProbScalars& S = sc[b];
+  S.g_rho = 0.0;
+  S.g_k = 0.0;
+  S.worst = 0.0;
+  S.status = 0;
+  S.its_total = 0;
+  S.solves = 0;
+  S.its_max = 0;
+  S.done = 1;
+}
+
+// Hessian directions take k_f, rho_f and the preconditioner of problem 0.
+__global__ void k_copy_dir_scalars(const ProbScalars* __restrict__ src, ProbScalars* __restrict__ dst,
+                                   int nd) {
+  int d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= nd) return;
+  ProbScalars S{};
+  S.kf = src[0].kf;
+  S.rhof = src[0].rhof;
+  S.kbar = src[0].kbar;
+  S.mmax = src[0].mmax;
+  S.done = 1;
+  dst[d] = S;
+}
+
+// Copy per-problem gradients out (device -> caller's device buffers).
+__global__ void k_emit_grads(const ProbScalars* __restrict__ sc, double* J, double* grho,
+                             double* gkf, int nb) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  if (J) J[b] = sc[b].J;
+  if (grho) grho[b] = sc[b].g_rho;
+  if (gkf) gkf[b] = sc[b].g_k;
+}
+
+// ------------------------------------------------------- real-field ops
+template <typename T, int N>
+struct RP {
+  static constexpr long long REAL = (long long)N * N * N;
+  static constexpr int NBLK = (REAL / 256 / 8) < 1024 ? (int)((REAL / 256 / 8) > 0 ? REAL / 256 / 8 : 1) : 1024;
+};
+
+// partial max of m
+template <typename T, int N>
+__global__ void __launch_bounds__(256) k_mmax(const T* __restrict__ m, long long m_bs,
+                                              double* __restrict__ part) {
+  __shared__ double red[4];
+  const int b = blockIdx.y;
+  double mx = 0.0;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < RP<T, N>::REAL;
+       i += (long long)gridDim.x * 256)
+    mx = fmax(mx, (double)m[b * m_bs + i]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    part_at(part, b, 0)[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+// lam = h3 (c - d); partial sum (c - d)^2
+template <typename T, int N>
+__global__ void __launch_bounds__(256) k_misfit(const T* __restrict__ c, const T* __restrict__ d,
+                                                T* __restrict__ lam, double h3,
+                                                double* __restrict__ part) {
+  __shared__ double red[NSLOT * 4];
+  const int b = blockIdx.y;
+  const long long off = (long long)b * RP<T, N>::REAL;
+  double acc[NSLOT] = {0.0, 0.0, 0.0, 0.0};
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < RP<T, N>::REAL;
+       i += (long long)gridDim.x * 256) {
+    const double r = (double)c[off + i] - (double)d[off + i];
+    lam[off + i] = (T)(h3 * r);
+    acc[0] += r * r;
+  }
+  block_sums<256>(acc, 1, red);
+  if (threadIdx.x == 0) part_at(part, b, 0)[blockIdx.x] = acc[0];
+}
+
+// Gaussian factors g[b][i][a][j] = exp(-d(x_j, c_ia)^2 / (2 sigma^2)),
+// minimum-image periodic distance (Sec. 2.1 initial condition, Sec. 4.1
+// basis of standard deviation sigma).
+__global__ void k_basis_factors(const double* __restrict__ centres, long long c_bs,
+                                double* __restrict__ g, int n, int n_p, double sigma) {
+  const int b = blockIdx.y;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n_p * 3 * n) return;
+  const int j = idx % n, a = (idx / n) % 3, i = idx / (3 * n);
+  const double two_pi = 6.283185307179586476925286766559;
+  const double x = two_pi * (double)j / (double)n;
+  double d = fabs(x - centres[b * c_bs + i * 3 + a]);
+  d = fmod(d, two_pi);
+  d = fmin(d, two_pi - d);
+  g[((size_t)b * n_p + i) * 3 * n + a * n + j] = exp(-d * d / (2.0 * sigma * sigma));
+}
+
+// c0 = Phi p: one workgroup per (x, y) row chunk; thread = z.
+template <typename T, int N>
+__global__ void __launch_bounds__(256) k_phi(const double* __restrict__ p, long long p_bs,
+                                             const double* __restrict__ g, long long g_bs,
+                                             T* __restrict__ out, long long out_bs, int n_p) {
+  constexpr int ROWS = 256 / N > 0 ? 256 / N : 1;
+  const int b = blockIdx.y;
+  const int z = threadIdx.x % N;
+  const int r = threadIdx.x / N;
+  const long long rowid = (long long)blockIdx.x * ROWS + r;
+  const int x = (int)(rowid / N), y = (int)(rowid % N);
+  const double* gb = g + b * g_bs;
+  double acc = 0.0;
+  for (int i = 0; i < n_p; ++i) {
+    const double* gi = gb + (size_t)i * 3 * N;
+    acc += p[b * p_bs + i] * gi[x] * gi[N + y] * gi[2 * N + z];
+  }
+  out[b * out_bs + rowid * N + z] = (T)acc;
+}
+
+// Partials of Phi^T lam: block = RB rows, thread = z (or several rows);
+// partphi[b][i][blk].
+template <typename T, int N>
+struct PhiT {
+  static constexpr int ROWS_T = 256 / N > 0 ? 256 / N : 1;  // rows handled at once
+  static constexpr int RB = 64 > ROWS_T ? 64 : ROWS_T;       // rows per block
+  static constexpr int NBLK = N * N / RB;
+};
+
+template <typename T, int N>
+__global__ void __launch_bounds__(256) k_phit(const T* __restrict__ lam, long long lam_bs,
+                                              const double* __restrict__ g, long long g_bs,
+                                              double* __restrict__ partphi, int n_p) {
+  using P = PhiT<T, N>;
+  __shared__ double red[NSLOT * 4];
+  const int b = blockIdx.y;
+  const int z = threadIdx.x % N;
+  const int r0 = threadIdx.x / N;
+  const double* gb = g + b * g_bs;
+  const T* lb = lam + b * lam_bs;
+  for (int i0 = 0; i0 < n_p; i0 += NSLOT) {
+    double acc[NSLOT] = {0.0, 0.0, 0.0, 0.0};
+    const int ni = min(NSLOT, n_p - i0);
+    for (int rr = r0; rr < P::RB; rr += P::ROWS_T) {
+      const long long rowid = (long long)blockIdx.x * P::RB + rr;
+      const int x = (int)(rowid / N), y = (int)(rowid % N);
+      const double l = (double)lb[rowid * N + z];
+      for (int q = 0; q < ni; ++q) {
+        const double* gi = gb + (size_t)(i0 + q) * 3 * N;
+        acc[q] += gi[x] * gi[N + y] * gi[2 * N + z] * l;
+      }
+    }
+    block_sums<256>(acc, ni, red);
+    if (threadIdx.x == 0)
+      for (int q = 0; q < ni; ++q)
+        partphi[((size_t)b * n_p + i0 + q) * P::NBLK + blockIdx.x] = acc[q];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_phit_final(const double* __restrict__ partphi,
+                                                    int nblk, int n_p, double* __restrict__ out,
+                                                    long long out_bs) {
+  __shared__ double red[NSLOT * 4];
+  const int b = blockIdx.y, i = blockIdx.x;
+  double acc[NSLOT] = {0.0, 0.0, 0.0, 0.0};
+  const double* src = partphi + ((size_t)b * n_p + i) * nblk;
+  for (int k = threadIdx.x; k < nblk; k += 256) acc[0] += src[k];
+  block_sums<256>(acc, 1, red);
+  if (threadIdx.x == 0) out[b * out_bs + i] = acc[0];
+}
+
+}  // namespace
+}  // namespace tg

@@ -1,0 +1,477 @@
+// Host orchestration of the tumor forward, adjoint, tangent and
+// Gauss-Newton Hessian solves for one grid size and precision.
+//
+// Time stepping (paper, Sec. 3.3): Strang splitting, one step being
+//   a = R_{dt/2}(c^n);  (I - dt/2 A) b = (I + dt/2 A) a;  c^{n+1} = R_{dt/2}(b)
+// with A = div(k_f m grad .) and R the exact logistic flow.  Each
+// Crank-Nicolson system is solved by PCG in spectral space with the
+// constant-coefficient Fourier preconditioner (1 + dt/2 kbar |w|^2)^-1,
+// kbar = k_f max(m); x0 = a, stop when ||r|| <= rtol ||rhs|| (grid norms).
+// The adjoint is the exact transpose of these discrete steps (reduced
+// gradient of Sec. 3.1: state solve, adjoint solve, gradient), with
+// checkpointed states recomputed segment by segment.
+#pragma once
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "tg_kernels.h"
+
+namespace tg {
+
+#define TG_CHECK(x)                                 \
+  do {                                              \
+    hipError_t e_ = (x);                            \
+    if (e_ != hipSuccess) return e_;                \
+  } while (0)
+#define TG_LAUNCH_CHECK() TG_CHECK(hipGetLastError())
+
+template <typename T, int N>
+class Solver final : public ISolver {
+  static constexpr int C = sizeof(T) == 4 ? 32 : 16;  // pencils per x/y workgroup
+  using SX = SP<T, N, C, 0>;
+  using SY = SP<T, N, C, 1>;
+  using Z = ZP<T, N>;
+  using W = PW<T, N>;
+  using RPc = RP<T, N>;
+  using PT = PhiT<T, N>;
+  static constexpr long long REAL = (long long)N * N * N;
+  static constexpr long long SPECN = (long long)N * N * (N / 2);
+
+  // A batch of independent PCG systems sharing one launch.
+  struct Ctx {
+    cx<T>* X; cx<T>* R; cx<T>* P; cx<T>* Q; cx<T>* T1; cx<T>* T2; cx<T>* T3; cx<T>* S;
+    ProbScalars* sc;
+    double* part;
+    int nb;
+    const T* m; long long m_bs;
+    long long traj_bs;  // batch stride of stored states (0: shared trajectory)
+  };
+
+ public:
+  Solver(const SolverDims& d, const Workspace& w) : d_(d), w_(w) {
+    dt_ = d.T / d.nt;
+    tau_ = 0.5 * dt_;
+    const double h = 2.0 * M_PI / N;
+    h3_ = h * h * h;
+    hsc_.resize(d.batch + d.dirs);
+    its_est_ = 8;
+  }
+
+  // ------------------------------------------------------------ forward
+  hipError_t forward(const double* p, const double* rho, const double* kf, const void* m,
+                     void* cT, hipStream_t st) override {
+    st_ = st;
+    call_status_ = 0;
+    m_ = (const T*)m;
+    cT_ = (T*)cT;
+    Ctx c = prim();
+    stat_sc_ = c.sc;
+    stat_nb_ = c.nb;
+    k_init_scalars<<<(d_.batch + 63) / 64, 64, 0, st_>>>(w_.sc, rho, 1, kf, 1, d_.batch);
+    TG_LAUNCH_CHECK();
+    k_mmax<T, N><<<dim3(RPc::NBLK, d_.batch), 256, 0, st_>>>(m_, REAL, w_.part);
+    TG_LAUNCH_CHECK();
+    k_finalize<FIN_MMAX><<<d_.batch, 256, 0, st_>>>(w_.sc, w_.part, RPc::NBLK, 1.0, 0.0, 0);
+    TG_LAUNCH_CHECK();
+    const int nf = d_.n_p * 3 * N;
+    k_basis_factors<<<dim3((nf + 255) / 256, d_.batch), 256, 0, st_>>>(
+        w_.centres, (long long)d_.n_p * 3, w_.gfac, N, d_.n_p, d_.sigma);
+    TG_LAUNCH_CHECK();
+    constexpr int ROWS = 256 / N > 0 ? 256 / N : 1;
+    k_phi<T, N><<<dim3(N * N / ROWS, d_.batch), 256, 0, st_>>>(
+        p, d_.n_p, w_.gfac, (long long)d_.n_p * 3 * N, ck(0), REAL, d_.n_p);
+    TG_LAUNCH_CHECK();
+    TG_CHECK(fwd_steps(c, 0, d_.nt, /*initial=*/true));
+    live_seg_ = d_.nseg - 1;
+    return hipSuccess;
+  }
+
+  // ------------------------------------------------------------ adjoint
+  hipError_t vjp(const void* lamT, const void* cobs, double* J, double* gp, double* grho,
+                 double* gkf, hipStream_t st) override {
+    st_ = st;
+    call_status_ = 0;
+    Ctx c = prim();
+    stat_sc_ = c.sc;
+    stat_nb_ = c.nb;
+    k_reset_call<<<(d_.batch + 63) / 64, 64, 0, st_>>>(w_.sc, d_.batch);
+    TG_LAUNCH_CHECK();
+    const T* lt = (const T*)lamT;
+    if (cobs != nullptr) {
+      k_misfit<T, N><<<dim3(RPc::NBLK, d_.batch), 256, 0, st_>>>(cT_, (const T*)cobs, lam(0),
+                                                                h3_, w_.part);
+      TG_LAUNCH_CHECK();
+      k_finalize<FIN_J><<<d_.batch, 256, 0, st_>>>(w_.sc, w_.part, RPc::NBLK, 0.5 * h3_, 0, 0);
+      TG_LAUNCH_CHECK();
+      lt = lam(0);
+    }
+    TG_CHECK(adjoint_sweep(c, lt, REAL, /*gn=*/false));
+    TG_CHECK(phit(c, gp));
+    k_emit_grads<<<(d_.batch + 63) / 64, 64, 0, st_>>>(w_.sc, cobs ? J : nullptr, grho, gkf,
+                                                       d_.batch);
+    TG_LAUNCH_CHECK();
+    return hipSuccess;
+  }
+
+  // ------------------------------------------------- Gauss-Newton H v
+  hipError_t hessvec(int ndir, const double* V, double* HV, hipStream_t st) override {
+    st_ = st;
+    call_status_ = 0;
+    Ctx dc = dirs(ndir);
+    stat_sc_ = dc.sc;
+    stat_nb_ = ndir;
+    // direction scalars inherit k_f, rho_f, kbar of problem 0
+    k_copy_dir_scalars<<<(ndir + 63) / 64, 64, 0, st_>>>(w_.sc, dc.sc, ndir);
+    TG_LAUNCH_CHECK();
+    constexpr int ROWS = 256 / N > 0 ? 256 / N : 1;
+    // dc0 = Phi v for each direction
+    k_phi<T, N><<<dim3(N * N / ROWS, ndir), 256, 0, st_>>>(V, d_.n_p, w_.gfac, 0, lam(0),
+                                                          REAL, d_.n_p);
+    TG_LAUNCH_CHECK();
+    // tangent sweep, forward in time
+    for (int j = 0; j < d_.nseg; ++j) {
+      TG_CHECK(ensure_segment(j));
+      const int n0 = j * d_.s, n1 = std::min(n0 + d_.s, d_.nt);
+      for (int n = n0; n < n1; ++n) {
+        ZArgs a = zargs(dc);
+        if (n == 0) {
+          a.Cin = lam(0); a.cin_bs = REAL;
+          a.Cn = cn_ptr(0); a.cn_bs = 0;
+          launch_z<ZS_TAN_FIRST>(a, dc.nb);
+        } else {
+          TG_CHECK(inv_xy(dc, dc.X, dc.T1));
+          a.Xs = dc.T1;
+          a.Bn = bprev_ptr(n); a.bn_bs = 0;
+          launch_z<ZS_TAN>(a, dc.nb);
+        }
+        TG_LAUNCH_CHECK();
+        TG_CHECK(step_solve(dc, /*adj=*/false));
+      }
+    }
+    {
+      TG_CHECK(inv_xy(dc, dc.X, dc.T1));
+      ZArgs a = zargs(dc);
+      a.Xs = dc.T1;
+      a.Bn = bn_ptr(d_.nt - 1); a.bn_bs = 0;
+      a.Cst = lam(0); a.cst_bs = REAL;
+      a.out_scale = h3_;
+      launch_z<ZS_TAN_LAST>(a, dc.nb);
+      TG_LAUNCH_CHECK();
+    }
+    TG_CHECK(adjoint_sweep(dc, lam(0), REAL, /*gn=*/true));
+    TG_CHECK(phit(dc, HV, /*g_bs=*/0));
+    return hipSuccess;
+  }
+
+  int last_status() const override { return call_status_; }
+
+  hipError_t read_stats(CallStats* out, hipStream_t st) override {
+    const int nb = stat_nb_;
+    if (stat_sc_ == nullptr) {
+      *out = CallStats{0, 0, 0, 0, 0.0};
+      return hipSuccess;
+    }
+    TG_CHECK(hipMemcpyAsync(hsc_.data(), stat_sc_, nb * sizeof(ProbScalars), hipMemcpyDeviceToHost, st));
+    TG_CHECK(hipStreamSynchronize(st));
+    CallStats s{0, 0, 0, 0, 0.0};
+    for (int b = 0; b < nb; ++b) {
+      s.solves += hsc_[b].solves;
+      s.its_total += hsc_[b].its_total;
+      s.its_max = std::max(s.its_max, hsc_[b].its_max);
+      s.status |= hsc_[b].status;
+      s.worst_rel_residual = std::max(s.worst_rel_residual, hsc_[b].worst);
+    }
+    *out = s;
+    return hipSuccess;
+  }
+
+ private:
+  // ----------------------------------------------------------- layout
+  Ctx prim() {
+    Ctx c;
+    cx<T>** sp = (cx<T>**)w_.spec;
+    c.X = sp[0]; c.R = sp[1]; c.P = sp[2]; c.Q = sp[3];
+    c.T1 = sp[4]; c.T2 = sp[5]; c.T3 = sp[6]; c.S = sp[7];
+    c.sc = w_.sc; c.part = w_.part; c.nb = d_.batch;
+    c.m = m_; c.m_bs = REAL; c.traj_bs = REAL;
+    return c;
+  }
+  Ctx dirs(int ndir) {
+    Ctx c;
+    cx<T>** sp = (cx<T>**)w_.dspec;
+    c.X = sp[0]; c.R = sp[1]; c.P = sp[2]; c.Q = sp[3];
+    c.T1 = sp[4]; c.T2 = sp[5]; c.T3 = sp[6]; c.S = sp[7];
+    c.sc = w_.sc + d_.batch;
+    c.part = w_.part + (size_t)d_.batch * NSLOT * MAXBLK;
+    c.nb = ndir;
+    c.m = m_; c.m_bs = 0; c.traj_bs = 0;
+    return c;
+  }
+  T* ck(int j) { return (T*)w_.ck + (size_t)j * d_.batch * REAL; }
+  T* ckb(int j) { return (T*)w_.ckb + (size_t)j * d_.batch * REAL; }
+  T* segc(int i) { return (T*)w_.segc + (size_t)i * d_.batch * REAL; }
+  T* segb(int i) { return (T*)w_.segb + (size_t)i * d_.batch * REAL; }
+  T* lam(int b) { return (T*)w_.lam + (size_t)b * REAL; }
+  // stored states of the live segment
+  T* cn_ptr(int n) { return (n % d_.s == 0) ? ck(n / d_.s) : segc(n % d_.s); }
+  T* bn_ptr(int n) { return segb(n % d_.s); }
+  // b^{n-1} for a step n of the live segment (n >= 1)
+  T* bprev_ptr(int n) { return (n % d_.s == 0) ? ckb(n / d_.s) : segb((n - 1) % d_.s); }
+
+  ZArgs zargs(const Ctx& c) {
+    ZArgs a{};
+    a.m = c.m; a.m_bs = c.m_bs;
+    a.sc = c.sc; a.part = c.part;
+    a.tau = tau_;
+    a.out_scale = 1.0;
+    a.Xs = c.T1;
+    a.Y2 = c.S;
+    return a;
+  }
+
+  template <int MODE>
+  void launch_z(const ZArgs& a, int nb) {
+    k_z_step<T, N, MODE><<<dim3(Z::NBLK, nb), Z::NT, 0, st_>>>(a);
+  }
+
+  // spectral X -> T1 rows ready for a z pass (x then y inverse, 1/n^3)
+  hipError_t inv_xy(const Ctx& c, cx<T>* X, cx<T>* Y) {
+    k_x_inv<T, N, C><<<dim3(SX::NBLK, c.nb), SX::NT, 0, st_>>>(X, Y);
+    TG_LAUNCH_CHECK();
+    k_y_plain<T, N, C, true><<<dim3(SY::NBLK, c.nb), SY::NT, 0, st_>>>(Y, nullptr);
+    TG_LAUNCH_CHECK();
+    return hipSuccess;
+  }
+
+  // matvec tail: U1 = T?, U2 = T? given; produces W1, W23 in place, V3 in V3buf
+  void matvec_mid(const Ctx& c, cx<T>* U1, cx<T>* U2, cx<T>* V3, int pred) {
+    k_y_inv_grad<T, N, C><<<dim3(SY::NBLK, c.nb), SY::NT, 0, st_>>>(U1, U2, V3, c.sc, pred);
+    k_z_matvec<T, N><<<dim3(Z::NBLK, c.nb), Z::NT, 0, st_>>>(U1, U2, V3, c.m, c.m_bs, c.sc, pred);
+    k_y_fwd_div<T, N, C><<<dim3(SY::NBLK, c.nb), SY::NT, 0, st_>>>(U1, U2, V3, c.sc, pred);
+  }
+
+  // After a boundary z kernel left the step's real-to-spectral rows in T1
+  // (and S for the adjoint): finish the transform into X, run the right-
+  // hand-side matvec and the PCG solve.
+  hipError_t step_solve(const Ctx& c, bool adj) {
+    k_y_plain<T, N, C, false><<<dim3(SY::NBLK, c.nb), SY::NT, 0, st_>>>(c.T1, adj ? c.S : nullptr);
+    TG_LAUNCH_CHECK();
+    k_x_fwd_state<T, N, C><<<dim3(SX::NBLK, c.nb), SX::NT, 0, st_>>>(c.T1, c.X, c.T2, c.T3,
+                                                                     adj ? c.S : nullptr);
+    TG_LAUNCH_CHECK();
+    matvec_mid(c, c.T2, c.T3, c.T1, 0);
+    TG_LAUNCH_CHECK();
+    if (adj)
+      k_x_fwd_div<T, N, C, XM_RHS_ADJ><<<dim3(SX::NBLK, c.nb), SX::NT, 0, st_>>>(
+          c.T2, c.T3, c.X, c.R, nullptr, c.sc, c.part, tau_, 0, 0);
+    else
+      k_x_fwd_div<T, N, C, XM_RHS_FWD><<<dim3(SX::NBLK, c.nb), SX::NT, 0, st_>>>(
+          c.T2, c.T3, c.X, c.R, nullptr, c.sc, c.part, tau_, 0, 0);
+    TG_LAUNCH_CHECK();
+    k_finalize<FIN_INIT><<<c.nb, 256, 0, st_>>>(c.sc, c.part, SX::NBLK, 1.0 / REAL, rtol(), d_.maxit);
+    TG_LAUNCH_CHECK();
+    return pcg_loop(c);
+  }
+
+  double rtol() const {
+    // FP32 arithmetic cannot certify residuals below a few hundred ulps:
+    // stop at the stagnation floor 50 eps_32 if rtol asks for less.
+    if (sizeof(T) == 4) return std::max(d_.rtol, 50.0 * 1.1920928955078125e-07);
+    return d_.rtol;
+  }
+
+  void pcg_iteration(const Ctx& c) {
+    k_x_inv_grad<T, N, C, 1><<<dim3(SX::NBLK, c.nb), SX::NT, 0, st_>>>(c.P, c.R, c.T1, c.T2, c.sc,
+                                                                       tau_, 1);
+    matvec_mid(c, c.T1, c.T2, c.T3, 1);
+    k_x_fwd_div<T, N, C, XM_PCG><<<dim3(SX::NBLK, c.nb), SX::NT, 0, st_>>>(
+        c.T1, c.T2, c.P, c.Q, nullptr, c.sc, c.part, tau_, 1, 0);
+    k_finalize<FIN_PQ><<<c.nb, 256, 0, st_>>>(c.sc, c.part, SX::NBLK, 1.0 / REAL, rtol(), d_.maxit);
+    k_pcg_update<T, N><<<dim3(W::NBLK, c.nb), 256, 0, st_>>>(c.X, c.R, c.P, c.Q, c.sc, c.part, tau_);
+    k_finalize<FIN_RZ><<<c.nb, 256, 0, st_>>>(c.sc, c.part, W::NBLK, 1.0 / REAL, rtol(), d_.maxit);
+  }
+
+  // Launch predicated iterations in chunks; synchronize only to read the
+  // done flags between chunks.
+  hipError_t pcg_loop(const Ctx& c) {
+    int launched = 0;
+    int chunk = std::max(1, its_est_);
+    int maxseen = 0;
+    while (launched < d_.maxit) {
+      const int k = std::min(chunk, d_.maxit - launched);
+      for (int i = 0; i < k; ++i) pcg_iteration(c);
+      TG_LAUNCH_CHECK();
+      launched += k;
+      TG_CHECK(hipMemcpyAsync(hsc_.data(), c.sc, c.nb * sizeof(ProbScalars), hipMemcpyDeviceToHost,
+                              st_));
+      TG_CHECK(hipStreamSynchronize(st_));
+      bool all = true;
+      for (int b = 0; b < c.nb; ++b) {
+        all = all && hsc_[b].done;
+        maxseen = std::max(maxseen, hsc_[b].its);
+        call_status_ |= hsc_[b].status;
+      }
+      if (all) break;
+      chunk = std::max(2, its_est_ / 4);
+    }
+    its_est_ = std::max(1, maxseen);
+    return hipSuccess;
+  }
+
+  // Forward steps n0..n1-1 from the stored c^{n0}.  initial: the first
+  // forward of a call (writes checkpoints, keeps the last segment); else a
+  // recompute of one segment (keeps its states).
+  hipError_t fwd_steps(const Ctx& c, int n0, int n1, bool initial) {
+    const int s = d_.s;
+    const int last_start = (d_.nseg - 1) * s;
+    for (int n = n0; n < n1; ++n) {
+      ZArgs a = zargs(c);
+      if (n == n0) {
+        a.Cin = cn_ptr_for(n, initial); a.cin_bs = c.traj_bs;
+        launch_z<ZS_FWD_FIRST>(a, c.nb);
+      } else {
+        TG_CHECK(inv_xy(c, c.X, c.T1));
+        a.Xs = c.T1;
+        if (n % s == 0) {
+          // segment boundary (initial forward only): checkpoint c^n, b^{n-1}
+          a.Cst = ck(n / s); a.cst_bs = c.traj_bs;
+          a.Bst = ckb(n / s); a.bst_bs = c.traj_bs;
+        } else if (!initial || n - 1 >= last_start) {
+          a.Cst = segc(n % s); a.cst_bs = c.traj_bs;
+          a.Bst = segb((n - 1) % s); a.bst_bs = c.traj_bs;
+        }
+        launch_z<ZS_FWD>(a, c.nb);
+      }
+      TG_LAUNCH_CHECK();
+      TG_CHECK(step_solve(c, false));
+    }
+    TG_CHECK(inv_xy(c, c.X, c.T1));
+    ZArgs a = zargs(c);
+    a.Xs = c.T1;
+    if (!initial || n1 - 1 >= last_start) {
+      a.Bst = segb((n1 - 1) % s); a.bst_bs = c.traj_bs;
+    }
+    if (initial) {
+      a.Cst = cT_; a.cst_bs = REAL;
+    }
+    launch_z<ZS_FWD_LAST>(a, c.nb);
+    TG_LAUNCH_CHECK();
+    return hipSuccess;
+  }
+  T* cn_ptr_for(int n, bool) { return ck(n / d_.s); }
+
+  // Make segment j's states live in segc/segb (recompute if needed).
+  hipError_t ensure_segment(int j) {
+    if (live_seg_ == j) return hipSuccess;
+    const int n0 = j * d_.s, n1 = std::min(n0 + d_.s, d_.nt);
+    TG_CHECK(fwd_steps(prim(), n0, n1, false));
+    live_seg_ = j;
+    return hipSuccess;
+  }
+
+  // Reverse sweep.  lamT: cotangent on c(T) ([nb][n^3], stride lam_bs).
+  // gn: Gauss-Newton adjoint (no rho/k_f accumulation).
+  hipError_t adjoint_sweep(const Ctx& c, const T* lamT, long long lam_bs, bool gn) {
+    for (int j = d_.nseg - 1; j >= 0; --j) {
+      TG_CHECK(ensure_segment(j));
+      const int n0 = j * d_.s, n1 = std::min(n0 + d_.s, d_.nt);
+      for (int n = n1 - 1; n >= n0; --n) {
+        ZArgs a = zargs(c);
+        a.want_grho = gn ? 0 : 1;
+        a.Bn = bn_ptr(n); a.bn_bs = c.traj_bs;
+        a.Cn = cn_ptr(n); a.cn_bs = c.traj_bs;
+        if (n == d_.nt - 1) {
+          a.Cin = lamT; a.cin_bs = lam_bs;
+          launch_z<ZS_ADJ_FIRST>(a, c.nb);
+        } else {
+          TG_CHECK(inv_xy(c, c.X, c.T1));
+          a.Xs = c.T1;
+          launch_z<ZS_ADJ>(a, c.nb);
+        }
+        TG_LAUNCH_CHECK();
+        if (!gn) {
+          k_finalize<FIN_GRHO><<<c.nb, 256, 0, st_>>>(c.sc, c.part, Z::NBLK, 1.0, 0, 0);
+          TG_LAUNCH_CHECK();
+        }
+        TG_CHECK(step_solve(c, true));
+        // lam_a = mu + tau k_f A_m mu; g_k += tau <A_m mu, a + b>
+        k_x_inv_grad<T, N, C, 0><<<dim3(SX::NBLK, c.nb), SX::NT, 0, st_>>>(c.X, nullptr, c.T1, c.T2,
+                                                                           c.sc, tau_, 0);
+        matvec_mid(c, c.T1, c.T2, c.T3, 0);
+        k_x_fwd_div<T, N, C, XM_POST_ADJ><<<dim3(SX::NBLK, c.nb), SX::NT, 0, st_>>>(
+            c.T1, c.T2, c.X, nullptr, c.S, c.sc, c.part, tau_, 0, gn ? 0 : 1);
+        TG_LAUNCH_CHECK();
+        if (!gn) {
+          k_finalize<FIN_GK><<<c.nb, 256, 0, st_>>>(c.sc, c.part, SX::NBLK, tau_ / REAL, 0, 0);
+          TG_LAUNCH_CHECK();
+        }
+      }
+    }
+    // tail of step 0: lam_0 = R'(c^0) lam_a, into lam()
+    TG_CHECK(inv_xy(c, c.X, c.T1));
+    ZArgs a = zargs(c);
+    a.want_grho = gn ? 0 : 1;
+    a.Xs = c.T1;
+    a.Cn = ck(0); a.cn_bs = c.traj_bs;
+    a.Cst = lam(0); a.cst_bs = REAL;
+    launch_z<ZS_ADJ_LAST>(a, c.nb);
+    TG_LAUNCH_CHECK();
+    if (!gn) {
+      k_finalize<FIN_GRHO><<<c.nb, 256, 0, st_>>>(c.sc, c.part, Z::NBLK, 1.0, 0, 0);
+      TG_LAUNCH_CHECK();
+    }
+    return hipSuccess;
+  }
+
+  // g[b] = Phi^T lam(b)
+  hipError_t phit(const Ctx& c, double* out, long long g_bs = -1) {
+    if (g_bs < 0) g_bs = (long long)d_.n_p * 3 * N;
+    k_phit<T, N><<<dim3(PT::NBLK, c.nb), 256, 0, st_>>>(lam(0), REAL, w_.gfac, g_bs, w_.partphi,
+                                                        d_.n_p);
+    TG_LAUNCH_CHECK();
+    k_phit_final<<<dim3(d_.n_p, c.nb), 256, 0, st_>>>(w_.partphi, PT::NBLK, d_.n_p, out, d_.n_p);
+    TG_LAUNCH_CHECK();
+    return hipSuccess;
+  }
+
+  SolverDims d_;
+  Workspace w_;
+  hipStream_t st_ = nullptr;
+  const T* m_ = nullptr;
+  T* cT_ = nullptr;
+  double dt_, tau_, h3_;
+  std::vector<ProbScalars> hsc_;
+  int its_est_;
+  int live_seg_ = -1;
+  int call_status_ = 0;
+  ProbScalars* stat_sc_ = nullptr;
+  int stat_nb_ = 0;
+};
+
+template <typename T>
+ISolver* make_solver_t(const SolverDims& d, const Workspace& w) {
+  switch (d.n) {
+    case 8: return new Solver<T, 8>(d, w);
+    case 16: return new Solver<T, 16>(d, w);
+    case 32: return new Solver<T, 32>(d, w);
+    case 64: return new Solver<T, 64>(d, w);
+    case 128: return new Solver<T, 128>(d, w);
+    case 256: return new Solver<T, 256>(d, w);
+    default: return nullptr;
+  }
+}
+
+template <typename T>
+hipError_t fill_twiddles() {
+  static cx<T> host[TW_N];
+  for (int k = 0; k < TW_N; ++k) {
+    const long double a = -2.0L * 3.14159265358979323846264338327950288L * (long double)k / TW_N;
+    host[k].x = (T)cosl(a);
+    host[k].y = (T)sinl(a);
+  }
+  if (sizeof(T) == 8) return hipMemcpyToSymbol(HIP_SYMBOL(g_tw64), host, sizeof(host));
+  return hipMemcpyToSymbol(HIP_SYMBOL(g_tw32), host, sizeof(host));
+}
+
+}  // namespace tg

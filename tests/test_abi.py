@@ -1,0 +1,105 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry
+point declared in include/tumorgrad.h, and rejects bad arguments on the
+host before launching anything."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1907_07774_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "tumorgrad.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(tg_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_function():
+    L = _lib.lib()
+    names = header_functions()
+    assert len(names) >= 11
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(_lib.EXPORTS) == set(names)
+
+
+def test_version_and_status_strings():
+    L = _lib.lib()
+    assert L.tg_version() == 1
+    for s in range(7):
+        assert len(L.tg_status_string(s)) > 0
+
+
+def make_desc(**kw):
+    cen = np.zeros((kw.pop("batch", 1), kw.pop("n_p", 8), 3))
+    d = dict(n=16, nt=4, T=1.0, sigma=0.2, pcg_rtol=1e-8, pcg_maxit=100, ckpt_stride=0,
+             prec=_lib.TG_FP64, batch=cen.shape[0], max_hvp_dirs=0)
+    d.update(kw)
+    desc = _lib.TgDesc(d["n"], d["nt"], d["T"], cen.shape[1],
+                       cen.ctypes.data_as(C.POINTER(C.c_double)), d["sigma"], d["pcg_rtol"],
+                       d["pcg_maxit"], d["ckpt_stride"], d["prec"], d["batch"], d["max_hvp_dirs"])
+    return desc, cen
+
+
+def create(**kw):
+    desc, cen = make_desc(**kw)
+    h = C.c_void_p()
+    st = _lib.lib().tg_plan_create(C.byref(desc), C.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("bad", [dict(n=12), dict(n=512), dict(n=4), dict(nt=0), dict(T=0.0),
+                                 dict(T=float("nan")), dict(sigma=-1.0), dict(pcg_rtol=0.0),
+                                 dict(pcg_rtol=1.5), dict(pcg_maxit=0), dict(ckpt_stride=-1),
+                                 dict(prec=7), dict(max_hvp_dirs=-2)])
+def test_plan_create_rejects_bad_descriptors(bad):
+    st, h = create(**bad)
+    assert st == _lib.TG_ERR_ARG
+    assert not h.value
+
+
+def test_plan_create_and_workspace_size():
+    L = _lib.lib()
+    st, h = create(n=32, nt=8, ckpt_stride=4, max_hvp_dirs=2)
+    assert st == _lib.TG_OK
+    nb = C.c_size_t()
+    assert L.tg_plan_workspace_bytes(h, C.byref(nb)) == _lib.TG_OK
+    # 8 spectra + 8 direction spectra + checkpoint/segment fields, FP64
+    field = 32 ** 3 * 8
+    assert nb.value >= (16 + 2 + 2 + 4 + 4 + 2) * field
+    # unbound plan: calls fail on the host without touching a GPU
+    assert L.tg_forward(h, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), C.c_void_p(8),
+                        C.c_void_p(8), None) == _lib.TG_ERR_WORKSPACE
+    assert L.tg_vjp(h, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), C.c_void_p(8),
+                    None) == _lib.TG_ERR_STATE
+    assert L.tg_hessvec_gn(h, 1, C.c_void_p(8), C.c_void_p(8), None) == _lib.TG_ERR_STATE
+    assert L.tg_hessvec_gn(h, 3, C.c_void_p(8), C.c_void_p(8), None) == _lib.TG_ERR_ARG
+    assert L.tg_plan_bind(h, None, nb.value) == _lib.TG_ERR_WORKSPACE
+    assert L.tg_plan_bind(h, C.c_void_p(4096 + 8), nb.value) == _lib.TG_ERR_WORKSPACE
+    assert L.tg_plan_bind(h, C.c_void_p(4096), nb.value - 1) == _lib.TG_ERR_WORKSPACE
+    assert L.tg_forward(h, None, None, None, None, None, None) == _lib.TG_ERR_ARG
+    L.tg_plan_destroy(h)
+
+
+def test_fp32_workspace_is_half_of_fp64():
+    L = _lib.lib()
+    sizes = []
+    for prec in (_lib.TG_FP64, _lib.TG_FP32_MIXED):
+        st, h = create(n=64, nt=8, prec=prec)
+        nb = C.c_size_t()
+        L.tg_plan_workspace_bytes(h, C.byref(nb))
+        sizes.append(nb.value)
+        L.tg_plan_destroy(h)
+    assert sizes[1] < 0.6 * sizes[0]
+
+
+def test_nonfinite_centres_rejected():
+    desc, cen = make_desc()
+    cen[0, 0, 0] = np.nan
+    h = C.c_void_p()
+    assert _lib.lib().tg_plan_create(C.byref(desc), C.byref(h)) == _lib.TG_ERR_ARG

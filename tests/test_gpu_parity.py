@@ -1,0 +1,236 @@
+"""GPU path vs the FP64 oracle, element by element, through the C-ABI.
+
+Tolerances: FP64 path 1e-10 relative (solves at rtol 1e-13); runs at the
+configurations' rtol 1e-8 are compared at 1e-7 (two PCG implementations
+stopped at 1e-8 differ by up to ~kappa 1e-8); FP32-mixed path 1e-4
+relative L2.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import tumor
+from paper_1907_07774_amd import _lib, api, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def case(n, g, seed, nt, rho, kf, scale_ic=True):
+    pr = inputs.problem(n, g, seed, nt=nt, rho_f=rho, k_f=kf)
+    p = pr.p
+    if scale_ic:
+        mx = tumor.phi(p, pr.centres, pr.sigma, n).max()
+        p = p / max(mx, 1.0)
+    return pr, p
+
+
+def oracle_setup(pr, rtol=1e-13):
+    return tumor.Setup(pr.m, pr.centres, pr.sigma, pr.rho_f, pr.k_f, pr.nt, rtol=rtol)
+
+
+def gpu_plan(pr, precision="fp64", rtol=1e-13, **kw):
+    return api.Plan(pr.n, pr.nt, pr.centres, pr.sigma, rtol=rtol, precision=precision, **kw)
+
+
+# ------------------------------------------------------------ forward
+@pytest.mark.parametrize("n", [8, 16, 32, 64])
+def test_reaction_only_fp64(n):
+    """k_f = 0: transforms must be exact round trips and the reaction the
+    exact logistic flow."""
+    print(f"case reaction_only n={n}", flush=True)
+    pr, p = case(n, 2, 1, 4, 9.0, 0.0)
+    tr = tumor.forward(oracle_setup(pr), p)
+    cT = gpu_plan(pr).forward(p, pr.rho_f, pr.k_f, pr.m).cpu().numpy()
+    assert rel(cT, tr.c[-1]) < 1e-13
+
+
+@pytest.mark.parametrize("n", [8, 16, 32, 64])
+def test_diffusion_only_fp64(n):
+    """rho_f = 0: pure Crank-Nicolson diffusion; mass is conserved."""
+    print(f"case diffusion_only n={n}", flush=True)
+    pr, p = case(n, 2, 2, 4, 0.0, 0.3)
+    tr = tumor.forward(oracle_setup(pr), p)
+    cT = gpu_plan(pr).forward(p, pr.rho_f, pr.k_f, pr.m).cpu().numpy()
+    assert rel(cT, tr.c[-1]) < 1e-10
+    assert abs(cT.sum() - tr.c[0].sum()) < 1e-12 * abs(tr.c[0].sum())
+
+
+@pytest.mark.parametrize("n,nt", [(16, 4), (32, 6), (64, 4)])
+def test_forward_fp64(n, nt):
+    print(f"case forward_fp64 n={n}", flush=True)
+    pr, p = case(n, 2, 3, nt, 10.0, 0.1)
+    tr = tumor.forward(oracle_setup(pr), p)
+    cT = gpu_plan(pr).forward(p, pr.rho_f, pr.k_f, pr.m).cpu().numpy()
+    assert rel(cT, tr.c[-1]) < 1e-10
+
+
+@pytest.mark.parametrize("n", [16, 64])
+def test_forward_fp32(n):
+    print(f"case forward_fp32 n={n}", flush=True)
+    pr, p = case(n, 2, 4, 6, 10.0, 0.1)
+    tr = tumor.forward(oracle_setup(pr), p)
+    cT = gpu_plan(pr, "fp32", rtol=1e-8).forward(p, pr.rho_f, pr.k_f, pr.m).cpu().numpy()
+    assert rel(cT, tr.c[-1]) < 1e-4
+
+
+# ----------------------------------------------------------- gradients
+def oracle_grad(pr, p, d, rtol=1e-13):
+    su = oracle_setup(pr, rtol)
+    return tumor.gradient(su, p, d)
+
+
+@pytest.mark.parametrize("n,nt,ckpt", [(16, 4, 0), (32, 5, 2), (64, 4, 3)])
+def test_gradient_fp64(n, nt, ckpt):
+    print(f"case gradient_fp64 n={n} ckpt={ckpt}", flush=True)
+    pr, p = case(n, 2, 5, nt, 8.0, 0.15)
+    d = inputs.threshold_mask(tumor.forward(oracle_setup(pr, 1e-10), inputs.perturbed_p(p, 5)).c[-1])
+    J, g, _ = oracle_grad(pr, p, d)
+    plan = gpu_plan(pr, ckpt_stride=ckpt)
+    plan.forward(p, pr.rho_f, pr.k_f, pr.m)
+    Jg, gp, gr, gk = plan.adjoint_misfit(d)
+    assert abs(float(Jg) - J) < 1e-10 * abs(J)
+    assert rel(gp.cpu().numpy(), g.g_p) < 1e-10
+    assert abs(float(gr) - g.g_rho) < 1e-10 * abs(g.g_rho)
+    assert abs(float(gk) - g.g_k) < 1e-10 * abs(g.g_k)
+
+
+@pytest.mark.parametrize("n", [16, 64])
+def test_gradient_fp32(n):
+    print(f"case gradient_fp32 n={n}", flush=True)
+    pr, p = case(n, 2, 6, 4, 8.0, 0.15)
+    d = inputs.threshold_mask(tumor.forward(oracle_setup(pr, 1e-10), inputs.perturbed_p(p, 6)).c[-1])
+    J, g, _ = oracle_grad(pr, p, d)
+    plan = gpu_plan(pr, "fp32", rtol=1e-8, ckpt_stride=2)
+    plan.forward(p, pr.rho_f, pr.k_f, pr.m)
+    Jg, gp, gr, gk = plan.adjoint_misfit(d)
+    assert abs(float(Jg) - J) < 1e-4 * abs(J)
+    assert rel(gp.cpu().numpy(), g.g_p) < 1e-4
+    assert abs(float(gr) - g.g_rho) < 1e-4 * abs(g.g_rho)
+    assert abs(float(gk) - g.g_k) < 1e-4 * abs(g.g_k)
+
+
+def test_vjp_with_given_cotangent_fp64():
+    print("case vjp_cotangent", flush=True)
+    pr, p = case(16, 2, 7, 4, 6.0, 0.2)
+    su = oracle_setup(pr)
+    tr = tumor.forward(su, p)
+    lam = inputs.random_field(16, 7)
+    g = tumor.vjp(su, tr, lam)
+    plan = gpu_plan(pr)
+    plan.forward(p, pr.rho_f, pr.k_f, pr.m)
+    gp, gr, gk = plan.vjp(lam)
+    assert rel(gp.cpu().numpy(), g.g_p) < 1e-10
+    assert abs(float(gr) - g.g_rho) < 1e-10 * abs(g.g_rho)
+    assert abs(float(gk) - g.g_k) < 1e-10 * abs(g.g_k)
+
+
+def test_checkpointing_is_bitwise_identical_fp64():
+    """Recomputed segments reproduce the stored trajectory bit for bit."""
+    print("case ckpt_bitwise", flush=True)
+    pr, p = case(32, 2, 8, 7, 8.0, 0.1)
+    d = inputs.random_field(32, 8)
+    outs = []
+    for ck in (0, 1, 3):
+        plan = gpu_plan(pr, rtol=1e-10, ckpt_stride=ck)
+        plan.forward(p, pr.rho_f, pr.k_f, pr.m)
+        J, gp, gr, gk = plan.adjoint_misfit(d)
+        outs.append((float(J), gp.cpu().numpy(), float(gr), float(gk)))
+    for o in outs[1:]:
+        assert o[0] == outs[0][0] and o[2] == outs[0][2] and o[3] == outs[0][3]
+        assert np.array_equal(o[1], outs[0][1])
+
+
+# ----------------------------------------------------------------- HVP
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
+def test_gn_hessvec(precision, tol):
+    print(f"case hessvec {precision}", flush=True)
+    pr, p = case(16, 2, 9, 4, 6.0, 0.2)
+    su = oracle_setup(pr)
+    tr = tumor.forward(su, p)
+    V = inputs.hvp_directions(3, p.size, 9)
+    H_or = np.stack([tumor.gn_hvp(su, tr, v) for v in V])
+    plan = gpu_plan(pr, precision, rtol=1e-13 if precision == "fp64" else 1e-8,
+                    ckpt_stride=3, max_hvp_dirs=4)
+    plan.forward(p, pr.rho_f, pr.k_f, pr.m)
+    HV = plan.hessvec(V).cpu().numpy()
+    for i in range(3):
+        assert rel(HV[i], H_or[i]) < tol
+    # symmetry <H v, w> = <v, H w>
+    assert abs(HV[0] @ V[1] - V[0] @ HV[1]) < 10 * tol * np.linalg.norm(HV[0])
+
+
+# --------------------------------------------------------------- batch
+def test_batch_matches_single_problems_fp64():
+    print("case batch", flush=True)
+    probs = [case(16, 2, s, 4, 5.0 + s, 0.05 * (s + 1)) for s in range(3)]
+    prs = [q[0] for q in probs]
+    ps = [q[1] for q in probs]
+    cen = np.stack([q.centres for q in prs])
+    plan = api.Plan(16, 4, cen, prs[0].sigma, rtol=1e-12, batch=3)
+    m = np.stack([q.m for q in prs])
+    plan.forward(np.stack(ps), [q.rho_f for q in prs], [q.k_f for q in prs], m)
+    d = np.stack([inputs.random_field(16, 20 + s) for s in range(3)])
+    J, gp, gr, gk = plan.adjoint_misfit(d)
+    for s in range(3):
+        J1, g1, _ = oracle_grad(prs[s], ps[s], d[s], 1e-13)
+        assert abs(float(J[s]) - J1) < 1e-9 * abs(J1)
+        assert rel(gp[s].cpu().numpy(), g1.g_p) < 1e-9
+        assert abs(float(gr[s]) - g1.g_rho) < 1e-9 * abs(g1.g_rho)
+        assert abs(float(gk[s]) - g1.g_k) < 1e-9 * abs(g1.g_k)
+
+
+# ---------------------------------------------------------- error paths
+def test_maxit_reports_not_converged_and_writes_output():
+    pr, p = case(16, 2, 10, 2, 5.0, 0.3)
+    plan = api.Plan(16, 2, pr.centres, pr.sigma, rtol=1e-12, maxit=1)
+    with pytest.raises(_lib.TumorGradError) as ei:
+        plan.forward(p, pr.rho_f, pr.k_f, pr.m)
+    assert ei.value.status == _lib.TG_ERR_NOT_CONVERGED
+    assert plan.stats().status_bits & 1
+    assert np.isfinite(plan._keep[4].cpu().numpy()).all()
+
+
+def test_nan_input_reports_numeric():
+    pr, p = case(16, 2, 11, 2, 5.0, 0.3)
+    m = pr.m.copy()
+    m[3, 4, 5] = np.nan
+    plan = api.Plan(16, 2, pr.centres, pr.sigma, rtol=1e-8)
+    with pytest.raises(_lib.TumorGradError) as ei:
+        plan.forward(p, pr.rho_f, pr.k_f, m)
+    assert ei.value.status == _lib.TG_ERR_NUMERIC
+
+
+def test_vjp_before_forward_is_state_error():
+    pr, p = case(16, 2, 12, 2, 5.0, 0.3)
+    plan = gpu_plan(pr)
+    with pytest.raises(_lib.TumorGradError) as ei:
+        plan.vjp(np.zeros((16, 16, 16)))
+    assert ei.value.status == _lib.TG_ERR_STATE
+
+
+# ------------------------------------------------------------- autograd
+def test_autograd_function_fp64():
+    print("case autograd", flush=True)
+    pr, p = case(16, 2, 13, 4, 7.0, 0.1)
+    d = inputs.random_field(16, 13)
+    J, g, _ = oracle_grad(pr, p, d)
+    plan = gpu_plan(pr)
+    dev = torch.device("cuda:0")
+    pt = torch.tensor(p, dtype=torch.float64, device=dev, requires_grad=True)
+    rt = torch.tensor(pr.rho_f, dtype=torch.float64, device=dev, requires_grad=True)
+    kt = torch.tensor(pr.k_f, dtype=torch.float64, device=dev, requires_grad=True)
+    m = torch.tensor(pr.m, device=dev)
+    cT = api.TumorSolve.apply(pt, rt, kt, m, plan)
+    h3 = (2 * np.pi / 16) ** 3
+    loss = 0.5 * h3 * ((cT - torch.tensor(d, device=dev)) ** 2).sum()
+    loss.backward()
+    assert abs(loss.item() - J) < 1e-10 * J
+    assert rel(pt.grad.cpu().numpy(), g.g_p) < 1e-10
+    assert abs(rt.grad.item() - g.g_rho) < 1e-10 * abs(g.g_rho)
+    assert abs(kt.grad.item() - g.g_k) < 1e-10 * abs(g.g_k)
