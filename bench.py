@@ -1,0 +1,258 @@
+#!/usr/bin/env python3
+"""Benchmark: forward + adjoint gradient evaluations per second at 256^3.
+
+One step = one full gradient evaluation of the tumor calibration misfit
+(forward Strang/Crank-Nicolson solve from c0 = Phi p, misfit, checkpointed
+adjoint sweep with segment recompute, gradient with respect to p, rho_f and
+k_f), on synthetic inputs resident in HBM: a seeded white-matter phantom,
+64 Gaussian basis functions (sigma = 2 pi/30, spacing 1.5 sigma), rho_f and
+k_f drawn from the seed, nt = 32, T = 1, PCG rtol 1e-8, checkpoint stride 4,
+FP32 fields and transforms with FP64 reductions.  The plain FP64 path is
+timed beside it.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "fwd+adjoint gradient evals/sec @256³ (FP32-mixed vs FP64) + HBM GB/s"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--nt", type=int, default=32)
+    ap.add_argument("--g", type=int, default=4)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--ckpt", type=int, default=4)
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--timer-kernel", default="z_matvec")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (counter calibration)")
+    return ap.parse_args()
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("tg_kernels.h", "tg_fft.h"):
+        with open(os.path.join(ROOT, "paper_1907_07774_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel, n, prec):
+    """Measured HBM bytes per launch from the committed counter summary, if
+    it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            tab = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    ent = tab.get(f"{kernel}/{n}/{prec}")
+    if not ent or ent.get("source_hash") != kernel_source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def run_precision(torch, api, inputs, pr, c_obs, precision, args, steps, warmup, timer):
+    plan = api.Plan(pr.n, pr.nt, pr.centres, pr.sigma, T=pr.T, rtol=args.rtol,
+                    ckpt_stride=args.ckpt, precision=precision)
+    dev = torch.device("cuda:0")
+    dt = torch.float32 if precision == "fp32" else torch.float64
+    m = torch.tensor(pr.m, dtype=dt, device=dev)
+    p = torch.tensor(pr.p, dtype=torch.float64, device=dev)
+    rho = torch.tensor([pr.rho_f], dtype=torch.float64, device=dev)
+    kf = torch.tensor([pr.k_f], dtype=torch.float64, device=dev)
+    d = c_obs.to(dt)
+
+    def step():
+        plan.forward(p, rho, kf, m)
+        s1 = plan.stats()
+        J, gp, gr, gk = plan.adjoint_misfit(d)
+        s2 = plan.stats()
+        return J, gp, gr, gk, s1, s2
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    if timer:
+        plan.kernel_timer(timer)
+    st = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(st)
+    out = None
+    for _ in range(steps):
+        out = step()
+    e1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = e0.elapsed_time(e1)
+    tinfo = plan.kernel_timer_read() if timer else None
+    J, gp, gr, gk, s1, s2 = out
+    res = {
+        "ms_per_step": 1000.0 * wall / steps,
+        "event_ms_per_step": ev_ms / steps,
+        "value": steps / wall,
+        "J": float(J), "g_rho": float(gr), "g_kf": float(gk),
+        "g_p_norm": float(torch.linalg.norm(gp)),
+        "pcg_its_forward": s1.pcg_its_total, "solves_forward": s1.solves,
+        "pcg_its_adjoint": s2.pcg_its_total, "solves_adjoint": s2.solves,
+        "pcg_its_max": max(s1.pcg_its_max, s2.pcg_its_max),
+        "worst_rel_residual": max(s1.worst_rel_residual, s2.worst_rel_residual),
+        "gp": gp.detach().cpu().numpy(),
+    }
+    if tinfo:
+        ms, launches, work_bytes = tinfo
+        res["timer"] = {"kernel": timer, "ms": ms, "launches": launches,
+                        "work_bytes": work_bytes}
+    del plan
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(pr, res32):
+    """Time the FP64 oracle's per-iteration work at the same size (operator
+    and preconditioner applications), scaled by the PCG work of one
+    gradient as counted on the GPU run."""
+    import numpy as np
+    from oracle import spectral
+    n = pr.n
+    dt = pr.T / pr.nt
+    k = pr.k_f * pr.m
+    sym = spectral.precond_symbol(n, dt, pr.k_f * float(pr.m.max()))
+    u = np.array(pr.m, copy=True)
+    reps = 2
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        v = u - 0.5 * dt * spectral.diffusion(u, k)
+    t_mv = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        w = spectral.apply_precond(v, sym)
+    t_pc = (time.perf_counter() - t0) / reps
+    its = res32["pcg_its_forward"] + res32["pcg_its_adjoint"]
+    solves = res32["solves_forward"] + res32["solves_adjoint"]
+    adj_solves = pr.nt
+    mv_count = its + solves + adj_solves
+    t_grad = its * t_pc + mv_count * t_mv
+    del w
+    return {
+        "value": 1.0 / t_grad, "unit": "gradient evals/s", "cores": 1, "kind": "oracle",
+        "sample": (f"{reps} applications each of the FP64 oracle's Crank-Nicolson operator "
+                   f"({t_mv:.2f} s) and Fourier preconditioner ({t_pc:.2f} s) at {n}^3 "
+                   f"(numpy pocketfft, 1 thread), scaled by one gradient's PCG work on the GPU "
+                   f"run: {its} iterations, {mv_count} operator applications"),
+        "seconds_per_gradient": t_grad,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1907_07774_amd import api, inputs
+
+    pr = inputs.problem(args.n, args.g, args.seed, nt=args.nt, T=1.0)
+    # synthetic observation: threshold of a run with perturbed coefficients
+    obs_plan = api.Plan(pr.n, pr.nt, pr.centres, pr.sigma, rtol=args.rtol,
+                        ckpt_stride=args.ckpt, precision="fp32")
+    dev = torch.device("cuda:0")
+    cpo = obs_plan.forward(inputs.perturbed_p(pr.p, args.seed), pr.rho_f, pr.k_f,
+                           torch.tensor(pr.m, dtype=torch.float32, device=dev))
+    c_obs = (cpo > 0.5).to(torch.float64)
+    del obs_plan, cpo
+    torch.cuda.empty_cache()
+
+    if args.copy_probe_mib:
+        a = torch.empty(args.copy_probe_mib << 20, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    r32 = run_precision(torch, api, inputs, pr, c_obs, "fp32", args, args.steps, args.warmup,
+                        args.timer_kernel)
+    r64 = None
+    if not args.no_fp64:
+        r64 = run_precision(torch, api, inputs, pr, c_obs, "fp64", args, args.fp64_steps,
+                            min(args.warmup, 1), None)
+
+    roof = None
+    if "timer" in r32:
+        t = r32["timer"]
+        avg_ms = t["ms"] / max(t["launches"], 1)
+        achieved = t["work_bytes"] / (t["ms"] * 1e-3) / 1e9
+        traffic = load_traffic(t["kernel"], args.n, "fp32")
+        roof = {"bound": "hbm", "kernel": t["kernel"], "achieved": achieved,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": traffic, "avg_launch_ms": avg_ms, "launches": t["launches"],
+                "algorithmic_bytes_per_work_launch": t["work_bytes"] / max(t["launches"], 1)}
+
+    out = {
+        "metric": METRIC,
+        "value": r32["value"],
+        "unit": "gradient evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"tumor forward+adjoint gradient, {args.n}^3 periodic grid, nt={args.nt}, "
+                         f"T=1, {args.g ** 3} Gaussians, rho_f={pr.rho_f:.3f}, k_f={pr.k_f:.4f} "
+                         f"(seed {args.seed}), PCG rtol {args.rtol:g}, checkpoint stride "
+                         f"{args.ckpt}, FP32 fields/FFTs with FP64 reductions"),
+            "grid": args.n, "nt": args.nt, "n_p": args.g ** 3, "seed": args.seed,
+            "rho_f": pr.rho_f, "k_f": pr.k_f, "rtol": args.rtol, "ckpt_stride": args.ckpt,
+        },
+        "roofline": roof,
+        "pcg": {k: r32[k] for k in ("pcg_its_forward", "solves_forward", "pcg_its_adjoint",
+                                    "solves_adjoint", "pcg_its_max", "worst_rel_residual")},
+    }
+    if r64 is not None:
+        gp32, gp64 = r32["gp"], r64["gp"]
+        out["fp64"] = {
+            "value": r64["value"], "ms_per_step": r64["ms_per_step"],
+            "speedup_fp32_mixed_over_fp64": r32["value"] / r64["value"],
+            "fp32_vs_fp64_rel_err": {
+                "J": abs(r32["J"] - r64["J"]) / abs(r64["J"]),
+                "g_p": float(np.linalg.norm(gp32 - gp64) / np.linalg.norm(gp64)),
+                "g_rho": abs(r32["g_rho"] - r64["g_rho"]) / abs(r64["g_rho"]),
+                "g_kf": abs(r32["g_kf"] - r64["g_kf"]) / abs(r64["g_kf"]),
+            },
+            "pcg_its_forward": r64["pcg_its_forward"], "pcg_its_adjoint": r64["pcg_its_adjoint"],
+        }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(pr, r32)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

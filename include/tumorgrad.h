@@ -135,6 +135,20 @@ tg_status tg_hessvec_gn(tg_plan* plan, int ndir, const double* d_V, double* d_HV
 /* PCG statistics of the last call (synchronizes the plan's last stream). */
 tg_status tg_stats(tg_plan* plan, tg_solve_stats* out);
 
+/* Kernel timer for performance measurement.  Identifies one kernel of the
+ * PCG iteration (1: x-pass inverse with direction update, 2: y-pass inverse,
+ * 3: z-pass C2R * m * R2C, 4: y-pass forward, 5: x-pass forward with
+ * q = p - dt/2 A p, 6: PCG vector update; 0: off).  While enabled, every
+ * launch of that kernel is bracketed by HIP events on the plan's stream.
+ * tg_kernel_timer resets the counters. */
+tg_status tg_kernel_timer(tg_plan* plan, int kernel_id);
+
+/* Read the timer (synchronizes the recorded events): total event time in
+ * ms, number of timed launches, and the algorithmic HBM bytes those
+ * launches moved (launches that did work x fields read and written). */
+tg_status tg_kernel_timer_read(tg_plan* plan, double* total_ms, long long* launches,
+                               double* work_bytes);
+
 const char* tg_status_string(tg_status s);
 void tg_plan_destroy(tg_plan* plan);
 int tg_version(void);

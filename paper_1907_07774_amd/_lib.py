@@ -25,7 +25,8 @@ TG_FP32_MIXED = 1
 EXPORTS = (
     "tg_plan_create", "tg_plan_workspace_bytes", "tg_plan_bind", "tg_forward",
     "tg_vjp", "tg_adjoint_misfit", "tg_hessvec_gn", "tg_stats",
-    "tg_status_string", "tg_plan_destroy", "tg_version",
+    "tg_status_string", "tg_plan_destroy", "tg_version", "tg_kernel_timer",
+    "tg_kernel_timer_read",
 )
 
 
@@ -77,8 +78,11 @@ def lib():
     L.tg_plan_destroy.argtypes = [vp]
     L.tg_plan_destroy.restype = None
     L.tg_version.restype = C.c_int
+    L.tg_kernel_timer.argtypes = [vp, C.c_int]
+    L.tg_kernel_timer_read.argtypes = [vp, dp, C.POINTER(C.c_longlong), dp]
     for name in ("tg_plan_create", "tg_plan_workspace_bytes", "tg_plan_bind", "tg_forward",
-                 "tg_vjp", "tg_adjoint_misfit", "tg_hessvec_gn", "tg_stats"):
+                 "tg_vjp", "tg_adjoint_misfit", "tg_hessvec_gn", "tg_stats",
+                 "tg_kernel_timer", "tg_kernel_timer_read"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L

@@ -167,6 +167,22 @@ class Plan:
         return Stats(s.solves, s.pcg_its_total, s.pcg_its_max, s.status_bits,
                      s.worst_rel_residual)
 
+    KERNELS = {"x_inv_grad": 1, "y_inv_grad": 2, "z_matvec": 3, "y_fwd_div": 4,
+               "x_fwd_div": 5, "pcg_update": 6}
+
+    def kernel_timer(self, name: str | None):
+        """Bracket every launch of one PCG-iteration kernel with HIP events."""
+        self._bind()
+        kid = 0 if name is None else self.KERNELS[name]
+        _lib.check(_lib.lib().tg_kernel_timer(self._h, kid), "tg_kernel_timer")
+
+    def kernel_timer_read(self):
+        """(total ms, launches, algorithmic bytes moved by the timed launches)."""
+        ms, n, b = C.c_double(), C.c_longlong(), C.c_double()
+        _lib.check(_lib.lib().tg_kernel_timer_read(self._h, C.byref(ms), C.byref(n), C.byref(b)),
+                   "tg_kernel_timer_read")
+        return ms.value, n.value, b.value
+
     def _vecs(self, gp, gr, gk):
         if self.batch == 1:
             return gp, gr[0], gk[0]

@@ -235,6 +235,20 @@ tg_status tg_stats(tg_plan* plan, tg_solve_stats* out) {
   return TG_OK;
 }
 
+tg_status tg_kernel_timer(tg_plan* plan, int kernel_id) {
+  if (plan == nullptr || kernel_id < tg::KT_NONE || kernel_id > tg::KT_PCG_UPDATE) return TG_ERR_ARG;
+  if (!plan->solver) return TG_ERR_WORKSPACE;
+  return from_hip(plan->solver->timer_enable(kernel_id));
+}
+
+tg_status tg_kernel_timer_read(tg_plan* plan, double* total_ms, long long* launches,
+                               double* work_bytes) {
+  if (plan == nullptr || total_ms == nullptr || launches == nullptr || work_bytes == nullptr)
+    return TG_ERR_ARG;
+  if (!plan->solver) return TG_ERR_WORKSPACE;
+  return from_hip(plan->solver->timer_read(total_ms, launches, work_bytes));
+}
+
 void tg_plan_destroy(tg_plan* plan) { delete plan; }
 
 }  // extern "C"

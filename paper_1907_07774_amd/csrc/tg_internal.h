@@ -79,6 +79,19 @@ class ISolver {
   virtual hipError_t read_stats(CallStats* out, hipStream_t st) = 0;
   // OR of the PCG status bits the host saw during the last call
   virtual int last_status() const = 0;
+  // Event timing of one kernel of the PCG iteration (KT_* id; KT_NONE off).
+  virtual hipError_t timer_enable(int id) = 0;
+  virtual hipError_t timer_read(double* ms, long long* launches, double* work_bytes) = 0;
+};
+
+enum KernelId : int {
+  KT_NONE = 0,
+  KT_X_INV_GRAD = 1,
+  KT_Y_INV_GRAD = 2,
+  KT_Z_MATVEC = 3,
+  KT_Y_FWD_DIV = 4,
+  KT_X_FWD_DIV = 5,
+  KT_PCG_UPDATE = 6
 };
 
 // Phi^T partial-block count for grid size n (workspace sizing).

@@ -246,9 +246,16 @@ class Solver final : public ISolver {
 
   // matvec tail: U1 = T?, U2 = T? given; produces W1, W23 in place, V3 in V3buf
   void matvec_mid(const Ctx& c, cx<T>* U1, cx<T>* U2, cx<T>* V3, int pred) {
-    k_y_inv_grad<T, N, C><<<dim3(SY::NBLK, c.nb), SY::NT, 0, st_>>>(U1, U2, V3, c.sc, pred);
-    k_z_matvec<T, N><<<dim3(Z::NBLK, c.nb), Z::NT, 0, st_>>>(U1, U2, V3, c.m, c.m_bs, c.sc, pred);
-    k_y_fwd_div<T, N, C><<<dim3(SY::NBLK, c.nb), SY::NT, 0, st_>>>(U1, U2, V3, c.sc, pred);
+    const int work = pred ? 0 : c.nb;
+    timed(KT_Y_INV_GRAD, work, [&] {
+      k_y_inv_grad<T, N, C><<<dim3(SY::NBLK, c.nb), SY::NT, 0, st_>>>(U1, U2, V3, c.sc, pred);
+    });
+    timed(KT_Z_MATVEC, work, [&] {
+      k_z_matvec<T, N><<<dim3(Z::NBLK, c.nb), Z::NT, 0, st_>>>(U1, U2, V3, c.m, c.m_bs, c.sc, pred);
+    });
+    timed(KT_Y_FWD_DIV, work, [&] {
+      k_y_fwd_div<T, N, C><<<dim3(SY::NBLK, c.nb), SY::NT, 0, st_>>>(U1, U2, V3, c.sc, pred);
+    });
   }
 
   // After a boundary z kernel left the step's real-to-spectral rows in T1
@@ -282,14 +289,88 @@ class Solver final : public ISolver {
   }
 
   void pcg_iteration(const Ctx& c) {
-    k_x_inv_grad<T, N, C, 1><<<dim3(SX::NBLK, c.nb), SX::NT, 0, st_>>>(c.P, c.R, c.T1, c.T2, c.sc,
-                                                                       tau_, 1);
+    timed(KT_X_INV_GRAD, 0, [&] {
+      k_x_inv_grad<T, N, C, 1><<<dim3(SX::NBLK, c.nb), SX::NT, 0, st_>>>(c.P, c.R, c.T1, c.T2,
+                                                                         c.sc, tau_, 1);
+    });
     matvec_mid(c, c.T1, c.T2, c.T3, 1);
-    k_x_fwd_div<T, N, C, XM_PCG><<<dim3(SX::NBLK, c.nb), SX::NT, 0, st_>>>(
-        c.T1, c.T2, c.P, c.Q, nullptr, c.sc, c.part, tau_, 1, 0);
+    timed(KT_X_FWD_DIV, 0, [&] {
+      k_x_fwd_div<T, N, C, XM_PCG><<<dim3(SX::NBLK, c.nb), SX::NT, 0, st_>>>(
+          c.T1, c.T2, c.P, c.Q, nullptr, c.sc, c.part, tau_, 1, 0);
+    });
     k_finalize<FIN_PQ><<<c.nb, 256, 0, st_>>>(c.sc, c.part, SX::NBLK, 1.0 / REAL, rtol(), d_.maxit);
-    k_pcg_update<T, N><<<dim3(W::NBLK, c.nb), 256, 0, st_>>>(c.X, c.R, c.P, c.Q, c.sc, c.part, tau_);
+    timed(KT_PCG_UPDATE, 0, [&] {
+      k_pcg_update<T, N><<<dim3(W::NBLK, c.nb), 256, 0, st_>>>(c.X, c.R, c.P, c.Q, c.sc, c.part,
+                                                               tau_);
+    });
     k_finalize<FIN_RZ><<<c.nb, 256, 0, st_>>>(c.sc, c.part, W::NBLK, 1.0 / REAL, rtol(), d_.maxit);
+  }
+
+  // ------------------------------------------------------ kernel timer
+  // HIP events around every launch of one chosen kernel, on the stream it
+  // is launched on.  "work" counts problem-launches that did real work:
+  // non-predicated launches count at launch time, predicated PCG-loop
+  // launches count once the loop has read the iteration counts.
+  static double unit_bytes(int id) {
+    const double S = (double)REAL * sizeof(T);  // one field / packed spectrum
+    switch (id) {
+      case KT_X_INV_GRAD: return 5 * S;   // read r, p; write p, U1, U2
+      case KT_Y_INV_GRAD: return 5 * S;   // read U1, U2; write V1, V2, V3
+      case KT_Z_MATVEC: return 7 * S;     // read V1..V3, m; write H1..H3
+      case KT_Y_FWD_DIV: return 5 * S;    // read H1..H3; write W1, W23
+      case KT_X_FWD_DIV: return 4 * S;    // read W1, W23, p; write q
+      case KT_PCG_UPDATE: return 6 * S;   // read x, r, p, q; write x, r
+    }
+    return 0.0;
+  }
+
+ public:
+  hipError_t timer_enable(int id) override {
+    TG_CHECK(timer_flush());
+    if (tm_ev_.empty()) {
+      tm_ev_.resize(2 * TM_CAP);
+      for (auto& e : tm_ev_) TG_CHECK(hipEventCreate(&e));
+    }
+    tm_id_ = id;
+    tm_ms_ = 0.0;
+    tm_launches_ = 0;
+    tm_work_ = 0;
+    return hipSuccess;
+  }
+  hipError_t timer_read(double* ms, long long* launches, double* work_bytes) override {
+    TG_CHECK(timer_flush());
+    *ms = tm_ms_;
+    *launches = tm_launches_;
+    *work_bytes = (double)tm_work_ * unit_bytes(tm_id_);
+    return hipSuccess;
+  }
+
+ private:
+  static constexpr int TM_CAP = 1024;
+  template <class F>
+  void timed(int id, int work, F&& launch) {
+    if (id != tm_id_) {
+      launch();
+      return;
+    }
+    if (tm_used_ == TM_CAP) timer_flush();
+    hipEventRecord(tm_ev_[2 * tm_used_], st_);
+    launch();
+    hipEventRecord(tm_ev_[2 * tm_used_ + 1], st_);
+    ++tm_used_;
+    ++tm_launches_;
+    tm_work_ += work;
+  }
+  hipError_t timer_flush() {
+    if (tm_used_ == 0) return hipSuccess;
+    TG_CHECK(hipEventSynchronize(tm_ev_[2 * tm_used_ - 1]));
+    for (int i = 0; i < tm_used_; ++i) {
+      float ms = 0.f;
+      TG_CHECK(hipEventElapsedTime(&ms, tm_ev_[2 * i], tm_ev_[2 * i + 1]));
+      tm_ms_ += ms;
+    }
+    tm_used_ = 0;
+    return hipSuccess;
   }
 
   // Launch predicated iterations in chunks; synchronize only to read the
@@ -316,6 +397,11 @@ class Solver final : public ISolver {
       chunk = std::max(2, its_est_ / 4);
     }
     its_est_ = std::max(1, maxseen);
+    if (tm_id_ != KT_NONE) {
+      long long eff = 0;
+      for (int b = 0; b < c.nb; ++b) eff += hsc_[b].its;
+      tm_work_ += eff;
+    }
     return hipSuccess;
   }
 
@@ -447,6 +533,18 @@ class Solver final : public ISolver {
   int call_status_ = 0;
   ProbScalars* stat_sc_ = nullptr;
   int stat_nb_ = 0;
+  // kernel timer state
+  int tm_id_ = KT_NONE;
+  std::vector<hipEvent_t> tm_ev_;
+  int tm_used_ = 0;
+  double tm_ms_ = 0.0;
+  long long tm_launches_ = 0;
+  long long tm_work_ = 0;
+
+ public:
+  ~Solver() override {
+    for (auto& e : tm_ev_) hipEventDestroy(e);
+  }
 };
 
 template <typename T>

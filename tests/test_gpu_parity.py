@@ -22,6 +22,11 @@ def rel(a, b):
 
 
 def case(n, g, seed, nt, rho, kf, scale_ic=True):
+    """Parameters are chosen so the discrete solution stays near [0, 1]: on
+    coarse grids the spectral undershoot at the white-matter edge can push
+    c below -1/(E - 1), where the logistic step has its pole, and the
+    discrete dynamics blow up (a property of the discretization, reproduced
+    by the oracle, but no meaningful FP32 comparison)."""
     pr = inputs.problem(n, g, seed, nt=nt, rho_f=rho, k_f=kf)
     p = pr.p
     if scale_ic:
@@ -61,19 +66,19 @@ def test_diffusion_only_fp64(n):
     assert abs(cT.sum() - tr.c[0].sum()) < 1e-12 * abs(tr.c[0].sum())
 
 
-@pytest.mark.parametrize("n,nt", [(16, 4), (32, 6), (64, 4)])
-def test_forward_fp64(n, nt):
+@pytest.mark.parametrize("n,nt,rho,kf", [(16, 4, 6.0, 0.2), (32, 6, 10.0, 0.1), (64, 4, 10.0, 0.1)])
+def test_forward_fp64(n, nt, rho, kf):
     print(f"case forward_fp64 n={n}", flush=True)
-    pr, p = case(n, 2, 3, nt, 10.0, 0.1)
+    pr, p = case(n, 2, 3, nt, rho, kf)
     tr = tumor.forward(oracle_setup(pr), p)
     cT = gpu_plan(pr).forward(p, pr.rho_f, pr.k_f, pr.m).cpu().numpy()
     assert rel(cT, tr.c[-1]) < 1e-10
 
 
-@pytest.mark.parametrize("n", [16, 64])
-def test_forward_fp32(n):
+@pytest.mark.parametrize("n,rho,kf", [(16, 6.0, 0.2), (64, 10.0, 0.1)])
+def test_forward_fp32(n, rho, kf):
     print(f"case forward_fp32 n={n}", flush=True)
-    pr, p = case(n, 2, 4, 6, 10.0, 0.1)
+    pr, p = case(n, 2, 4, 4, rho, kf)
     tr = tumor.forward(oracle_setup(pr), p)
     cT = gpu_plan(pr, "fp32", rtol=1e-8).forward(p, pr.rho_f, pr.k_f, pr.m).cpu().numpy()
     assert rel(cT, tr.c[-1]) < 1e-4
@@ -168,7 +173,7 @@ def test_gn_hessvec(precision, tol):
 # --------------------------------------------------------------- batch
 def test_batch_matches_single_problems_fp64():
     print("case batch", flush=True)
-    probs = [case(16, 2, s, 4, 5.0 + s, 0.05 * (s + 1)) for s in range(3)]
+    probs = [case(16, 2, s + 1, 4, 4.0 + s, 0.05 * (s + 1)) for s in range(3)]
     prs = [q[0] for q in probs]
     ps = [q[1] for q in probs]
     cen = np.stack([q.centres for q in prs])
@@ -217,7 +222,7 @@ def test_vjp_before_forward_is_state_error():
 # ------------------------------------------------------------- autograd
 def test_autograd_function_fp64():
     print("case autograd", flush=True)
-    pr, p = case(16, 2, 13, 4, 7.0, 0.1)
+    pr, p = case(16, 2, 13, 4, 6.0, 0.2)
     d = inputs.random_field(16, 13)
     J, g, _ = oracle_grad(pr, p, d)
     plan = gpu_plan(pr)
