@@ -164,8 +164,22 @@ __device__ __forceinline__ void dftR(cx<T>* v, int s) {
 }
 
 // ------------------------------------------------------- Stockham stages
+// Barrier between LDS exchange phases: the whole workgroup, or only the
+// wavefront when every transform lives inside one wave (then waves run
+// independently and only need their own LDS writes ordered before reads).
+template <bool WAVE>
+__device__ __forceinline__ void lds_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // LDS addressing: element (position p, column c) lives at lds[p*PS + c*CS].
-template <typename T, int L, int E, bool INV, int PS, int CS, int Ns>
+template <typename T, int L, int E, bool INV, int PS, int CS, int Ns, bool WAVE = false>
 struct Stockham {
   static __device__ __forceinline__ void run(cx<T> (&v)[E], cx<T>* lds, int t, int col) {
     constexpr int R = (L / Ns >= E) ? E : (L / Ns);
@@ -196,20 +210,20 @@ struct Stockham {
 #pragma unroll
         for (int r = 0; r < R; ++r) lds[(base + r * Ns) * PS + col * CS] = v[b + r * NB];
       }
-      __syncthreads();
+      lds_sync<WAVE>();
 #pragma unroll
       for (int e = 0; e < E; ++e) v[e] = lds[(t + e * TT) * PS + col * CS];
-      __syncthreads();
-      Stockham<T, L, E, INV, PS, CS, Ns * R>::run(v, lds, t, col);
+      lds_sync<WAVE>();
+      Stockham<T, L, E, INV, PS, CS, Ns * R, WAVE>::run(v, lds, t, col);
     }
   }
 };
 
 // Full L-point FFT of the values held by (t, col); in and out mapping:
 // v[e] <-> position t + (L/E) e.
-template <typename T, int L, int E, bool INV, int PS, int CS>
+template <typename T, int L, int E, bool INV, int PS, int CS, bool WAVE = false>
 __device__ __forceinline__ void fft(cx<T> (&v)[E], cx<T>* lds, int t, int col) {
-  Stockham<T, L, E, INV, PS, CS, 1>::run(v, lds, t, col);
+  Stockham<T, L, E, INV, PS, CS, 1, WAVE>::run(v, lds, t, col);
 }
 
 // Elements-per-thread choice for an L-point transform.

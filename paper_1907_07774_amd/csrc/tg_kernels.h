@@ -156,55 +156,66 @@ k_x_inv_grad(cx<T>* __restrict__ P, const cx<T>* __restrict__ Rr, cx<T>* __restr
 }
 
 // ---- y pass, inverse: V1 = IFFT_y(U1) (in place), V2 = IFFT_y(i wy U2)
-// (in place), V3 = IFFT_y(U2).
+// (in place), V3 = IFFT_y(U2).  Both inputs are loaded before any FFT.
 template <typename T, int N, int C>
 __global__ void __launch_bounds__((SP<T, N, C, 1>::NT))
 k_y_inv_grad(cx<T>* __restrict__ U1, cx<T>* __restrict__ U2, cx<T>* __restrict__ V3,
              const ProbScalars* __restrict__ sc, int pred) {
   SP_SETUP(1)
   if (pred && sc[b].done) return;
-  cx<T> v[E], w[E];
+  cx<T> v[E], u[E], w[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = U1[base + (t + TT * e) * S::PSTR];
+  for (int e = 0; e < E; ++e) {
+    v[e] = U1[base + (t + TT * e) * S::PSTR];
+    u[e] = U2[base + (t + TT * e) * S::PSTR];
+  }
   fft<T, N, E, true, C, 1>(v, lds, t, col);
 #pragma unroll
   for (int e = 0; e < E; ++e) U1[base + (t + TT * e) * S::PSTR] = v[e];
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    v[e] = U2[base + (t + TT * e) * S::PSTR];
-    w[e] = mul_i(v[e], (T)wfull<N>(t + TT * e));
-  }
-  fft<T, N, E, true, C, 1>(v, lds, t, col);
+  for (int e = 0; e < E; ++e) w[e] = mul_i(u[e], (T)wfull<N>(t + TT * e));
+  fft<T, N, E, true, C, 1>(u, lds, t, col);
 #pragma unroll
-  for (int e = 0; e < E; ++e) V3[base + (t + TT * e) * S::PSTR] = v[e];
+  for (int e = 0; e < E; ++e) V3[base + (t + TT * e) * S::PSTR] = u[e];
   fft<T, N, E, true, C, 1>(w, lds, t, col);
 #pragma unroll
   for (int e = 0; e < E; ++e) U2[base + (t + TT * e) * S::PSTR] = w[e];
 }
 
 // ---- y pass, forward: W1 = FFT_y(H1) (in place), W23 = i wy FFT_y(H2) +
-// FFT_y(H3) (into H2).
+// FFT_y(H3) (into H2).  FP32 loads all three inputs before any FFT.
 template <typename T, int N, int C>
 __global__ void __launch_bounds__((SP<T, N, C, 1>::NT))
 k_y_fwd_div(cx<T>* __restrict__ H1, cx<T>* __restrict__ H2, const cx<T>* __restrict__ H3,
             const ProbScalars* __restrict__ sc, int pred) {
   SP_SETUP(1)
   if (pred && sc[b].done) return;
-  cx<T> v[E], w[E];
+  constexpr bool PRE = sizeof(T) == 4;
+  cx<T> v[E], a[E], c[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = H1[base + (t + TT * e) * S::PSTR];
+  for (int e = 0; e < E; ++e) {
+    v[e] = H1[base + (t + TT * e) * S::PSTR];
+    if (PRE) {
+      a[e] = H2[base + (t + TT * e) * S::PSTR];
+      c[e] = H3[base + (t + TT * e) * S::PSTR];
+    }
+  }
   fft<T, N, E, false, C, 1>(v, lds, t, col);
 #pragma unroll
   for (int e = 0; e < E; ++e) H1[base + (t + TT * e) * S::PSTR] = v[e];
+  if (!PRE) {
 #pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = H2[base + (t + TT * e) * S::PSTR];
-  fft<T, N, E, false, C, 1>(v, lds, t, col);
+    for (int e = 0; e < E; ++e) a[e] = H2[base + (t + TT * e) * S::PSTR];
+  }
+  fft<T, N, E, false, C, 1>(a, lds, t, col);
+  if (!PRE) {
 #pragma unroll
-  for (int e = 0; e < E; ++e) w[e] = H3[base + (t + TT * e) * S::PSTR];
-  fft<T, N, E, false, C, 1>(w, lds, t, col);
+    for (int e = 0; e < E; ++e) c[e] = H3[base + (t + TT * e) * S::PSTR];
+  }
+  fft<T, N, E, false, C, 1>(c, lds, t, col);
 #pragma unroll
   for (int e = 0; e < E; ++e)
-    H2[base + (t + TT * e) * S::PSTR] = mul_i(v[e], (T)wfull<N>(t + TT * e)) + w[e];
+    H2[base + (t + TT * e) * S::PSTR] = mul_i(a[e], (T)wfull<N>(t + TT * e)) + c[e];
 }
 
 // ---- x pass, forward, divergence epilogue of the diffusion matvec:
@@ -229,10 +240,11 @@ k_x_fwd_div(const cx<T>* __restrict__ W1, const cx<T>* __restrict__ W23, cx<T>* 
   const double wgt = kz == 0 ? 1.0 : 2.0;
   cx<T> a[E], c[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) a[e] = W1[base + (t + TT * e) * S::PSTR];
+  for (int e = 0; e < E; ++e) {
+    a[e] = W1[base + (t + TT * e) * S::PSTR];
+    c[e] = W23[base + (t + TT * e) * S::PSTR];
+  }
   fft<T, N, E, false, C, 1>(a, lds, t, col);
-#pragma unroll
-  for (int e = 0; e < E; ++e) c[e] = W23[base + (t + TT * e) * S::PSTR];
   fft<T, N, E, false, C, 1>(c, lds, t, col);
   const T tk = (T)(tau * sc[b].kf);
   double acc[NSLOT] = {0.0, 0.0, 0.0, 0.0};
@@ -383,17 +395,39 @@ struct ZP {
   static constexpr long long REAL = (long long)N * N * N;
 };
 
+// Mirror partner of the value held in register e of row-thread t:
+// X[L - k] for k = t + TT e.  For t >= 1 it sits in register E-1-e of
+// row-thread TT - t (same wave, exchanged with a lane shuffle); for t = 0
+// in the thread's own register E - e.
+template <typename T>
+__device__ __forceinline__ cx<T> shfl_cx(cx<T> v, int src, int width) {
+  return mk(__shfl(v.x, src, width), __shfl(v.y, src, width));
+}
+
+template <typename T, int TT, int E>
+__device__ __forceinline__ void mirror_vals(const cx<T> (&v)[E], cx<T> (&m)[E], int t) {
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const cx<T> own = v[(E - e) % E];
+    if constexpr (TT == 1) {
+      m[e] = own;
+    } else {
+      const cx<T> other = shfl_cx(v[E - 1 - e], (TT - t) & (TT - 1), TT);
+      m[e] = (t == 0) ? own : other;
+    }
+  }
+}
+
 // Unnormalized C2R of one packed row: in v[e] = Y[k], k = t + TT e;
-// out v[e] = n (x[2j] + i x[2j+1]), j = t + TT e.
+// out v[e] = n (x[2j] + i x[2j+1]), j = t + TT e.  All exchanges stay
+// inside the row's wave.
 template <typename T, int N, int E>
 __device__ __forceinline__ void c2r_row(cx<T> (&v)[E], cx<T>* lds, int t, int row) {
   using Z = ZP<T, N>;
   static_assert(E == Z::E, "row register count");
   constexpr int L = Z::L, TT = Z::TT;
-  cx<T>* lr = lds + row * Z::PITCH;
-#pragma unroll
-  for (int e = 0; e < E; ++e) lr[t + TT * e] = v[e];
-  __syncthreads();
+  cx<T> mr[E];
+  mirror_vals<T, TT, E>(v, mr, t);
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int k = t + TT * e;
@@ -402,7 +436,7 @@ __device__ __forceinline__ void c2r_row(cx<T> (&v)[E], cx<T>* lds, int t, int ro
       // X0 = Re Y0, X_{n/2} = Im Y0
       v[e] = mk(xk.x + xk.y, xk.x - xk.y);
     } else {
-      const cx<T> xm = conjg(lr[L - k]);
+      const cx<T> xm = conjg(mr[e]);
       const cx<T> sum = xk + xm, dif = xk - xm;
       // i W_n^{-k} dif, W_n^{-k} = conj(tw)
       const cx<T> wk = conjg(twiddle<T, false, N>(k));
@@ -410,8 +444,8 @@ __device__ __forceinline__ void c2r_row(cx<T> (&v)[E], cx<T>* lds, int t, int ro
       v[e] = sum + mk(-tdif.y, tdif.x);
     }
   }
-  __syncthreads();
-  fft<T, L, E, true, 1, Z::PITCH>(v, lds, t, row);
+  (void)L;
+  fft<T, L, E, true, 1, Z::PITCH, true>(v, lds, t, row);
 }
 
 // Unnormalized R2C of one row: in v[e] = x[2j] + i x[2j+1]; out v[e] =
@@ -421,11 +455,9 @@ __device__ __forceinline__ void r2c_row(cx<T> (&v)[E], cx<T>* lds, int t, int ro
   using Z = ZP<T, N>;
   static_assert(E == Z::E, "row register count");
   constexpr int L = Z::L, TT = Z::TT;
-  fft<T, L, E, false, 1, Z::PITCH>(v, lds, t, row);
-  cx<T>* lr = lds + row * Z::PITCH;
-#pragma unroll
-  for (int e = 0; e < E; ++e) lr[t + TT * e] = v[e];
-  __syncthreads();
+  fft<T, L, E, false, 1, Z::PITCH, true>(v, lds, t, row);
+  cx<T> mr[E];
+  mirror_vals<T, TT, E>(v, mr, t);
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int k = t + TT * e;
@@ -433,14 +465,14 @@ __device__ __forceinline__ void r2c_row(cx<T> (&v)[E], cx<T>* lds, int t, int ro
     if (k == 0) {
       v[e] = mk(zk.x + zk.y, zk.x - zk.y);
     } else {
-      const cx<T> zm = conjg(lr[L - k]);
+      const cx<T> zm = conjg(mr[e]);
       const cx<T> sum = zk + zm, dif = zk - zm;
       // X = (sum - i W^k dif) / 2
       const cx<T> td = cmul(twiddle<T, false, N>(k), dif);
       v[e] = scale(sum + mk(td.y, -td.x), T(0.5));
     }
   }
-  __syncthreads();
+  (void)L;
 }
 
 #define ZP_SETUP                                                        \
@@ -454,34 +486,53 @@ __device__ __forceinline__ void r2c_row(cx<T> (&v)[E], cx<T>* lds, int t, int ro
   (void)sbase;
 
 // ---- matvec core: for j = x, y, z: g_j = C2R(V_j) (V_z times i wz), times
-// m, R2C, (z: times i wz).  In place on V1..V3.
+// m, R2C, (z: times i wz).  In place on V1..V3.  rev walks the rows from
+// the last to the first (the y pass before it ends at the last rows, whose
+// output is then still in the last-level cache).  FP32 loads all three
+// rows up front.
 template <typename T, int N>
 __global__ void __launch_bounds__((ZP<T, N>::NT))
 k_z_matvec(cx<T>* __restrict__ V1, cx<T>* __restrict__ V2, cx<T>* __restrict__ V3,
-           const T* __restrict__ m, long long m_bs, const ProbScalars* __restrict__ sc, int pred) {
-  ZP_SETUP
+           const T* __restrict__ m, long long m_bs, const ProbScalars* __restrict__ sc, int pred,
+           int rev) {
+  using Z = ZP<T, N>;
+  constexpr int E = Z::E, TT = Z::TT;
+  __shared__ cx<T> lds[Z::RW * Z::PITCH];
+  const int b = blockIdx.y;
   if (pred && sc[b].done) return;
+  const int t = threadIdx.x % TT, row = threadIdx.x / TT;
+  const int bx = rev ? (int)gridDim.x - 1 - (int)blockIdx.x : (int)blockIdx.x;
+  const long long grow = (long long)bx * Z::RW + row;
+  const long long sbase = (long long)b * Z::SPEC + grow * Z::L;
   const cx<T>* mrow = reinterpret_cast<const cx<T>*>(m + b * m_bs + grow * N);
-  cx<T> mv[E], v[E];
+  cx<T>* Vs[3] = {V1 + sbase, V2 + sbase, V3 + sbase};
+  constexpr int PRE = sizeof(T) == 4 ? 3 : 1;  // rows held in registers at once
+  cx<T> mv[E], v[PRE][E];
 #pragma unroll
   for (int e = 0; e < E; ++e) mv[e] = mrow[t + TT * e];
-  cx<T>* Vs[3] = {V1, V2, V3};
+#pragma unroll
+  for (int j = 0; j < PRE; ++j)
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[j][e] = Vs[j][t + TT * e];
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
-    cx<T>* V = Vs[j] + sbase;
+    cx<T>(&u)[E] = v[PRE == 3 ? j : 0];
+    if (PRE == 1 && j > 0) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      v[e] = V[t + TT * e];
-      if (j == 2) v[e] = mul_i(v[e], (T)(t + TT * e));
+      for (int e = 0; e < E; ++e) u[e] = Vs[j][t + TT * e];
     }
-    c2r_row<T, N>(v, lds, t, row);
+    if (j == 2) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = mk(v[e].x * mv[e].x, v[e].y * mv[e].y);
-    r2c_row<T, N>(v, lds, t, row);
+      for (int e = 0; e < E; ++e) u[e] = mul_i(u[e], (T)(t + TT * e));
+    }
+    c2r_row<T, N>(u, lds, t, row);
+#pragma unroll
+    for (int e = 0; e < E; ++e) u[e] = mk(u[e].x * mv[e].x, u[e].y * mv[e].y);
+    r2c_row<T, N>(u, lds, t, row);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      if (j == 2) v[e] = mul_i(v[e], (T)(t + TT * e));
-      V[t + TT * e] = v[e];
+      if (j == 2) u[e] = mul_i(u[e], (T)(t + TT * e));
+      Vs[j][t + TT * e] = u[e];
     }
   }
 }
@@ -857,6 +908,15 @@ __global__ void k_copy_dir_scalars(const ProbScalars* __restrict__ src, ProbScal
   S.mmax = src[0].mmax;
   S.done = 1;
   dst[d] = S;
+}
+
+// dst = src over n elements of a packed spectrum batch (graph-safe copy).
+template <typename T>
+__global__ void __launch_bounds__(256) k_copy_spec(cx<T>* __restrict__ dst,
+                                                   const cx<T>* __restrict__ src, long long n) {
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (long long)gridDim.x * 256)
+    dst[i] = src[i];
 }
 
 // Copy per-problem gradients out (device -> caller's device buffers).

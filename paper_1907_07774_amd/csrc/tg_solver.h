@@ -251,7 +251,8 @@ class Solver final : public ISolver {
       k_y_inv_grad<T, N, C><<<dim3(SY::NBLK, c.nb), SY::NT, 0, st_>>>(U1, U2, V3, c.sc, pred);
     });
     timed(KT_Z_MATVEC, work, [&] {
-      k_z_matvec<T, N><<<dim3(Z::NBLK, c.nb), Z::NT, 0, st_>>>(U1, U2, V3, c.m, c.m_bs, c.sc, pred);
+      k_z_matvec<T, N><<<dim3(Z::NBLK, c.nb), Z::NT, 0, st_>>>(U1, U2, V3, c.m, c.m_bs, c.sc, pred,
+                                                               1);
     });
     timed(KT_Y_FWD_DIV, work, [&] {
       k_y_fwd_div<T, N, C><<<dim3(SY::NBLK, c.nb), SY::NT, 0, st_>>>(U1, U2, V3, c.sc, pred);
@@ -460,7 +461,13 @@ class Solver final : public ISolver {
   // gn: Gauss-Newton adjoint (no rho/k_f accumulation).
   hipError_t adjoint_sweep(const Ctx& c, const T* lamT, long long lam_bs, bool gn) {
     for (int j = d_.nseg - 1; j >= 0; --j) {
+      // A recompute of the primary context reuses its spectral buffers:
+      // park the adjoint state (X) in the real scratch field meanwhile
+      // (free once the first reverse step has consumed lambda_T).
+      const bool park = j < d_.nseg - 1 && live_seg_ != j && c.X == prim().X;
+      if (park) copy_spec(c, (cx<T>*)w_.lam, c.X);
       TG_CHECK(ensure_segment(j));
+      if (park) copy_spec(c, c.X, (cx<T>*)w_.lam);
       const int n0 = j * d_.s, n1 = std::min(n0 + d_.s, d_.nt);
       for (int n = n1 - 1; n >= n0; --n) {
         ZArgs a = zargs(c);
@@ -508,6 +515,12 @@ class Solver final : public ISolver {
       TG_LAUNCH_CHECK();
     }
     return hipSuccess;
+  }
+
+  void copy_spec(const Ctx& c, cx<T>* dst, const cx<T>* src) {
+    const long long n = (long long)c.nb * SPECN;
+    const int blocks = (int)std::min<long long>((n + 255) / 256, 4096);
+    k_copy_spec<T><<<blocks, 256, 0, st_>>>(dst, src, n);
   }
 
   // g[b] = Phi^T lam(b)
