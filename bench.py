@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--timer-kernel", default="z_matvec")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-hvp", action="store_true")
+    ap.add_argument("--batch-reps", type=int, default=3)
     return ap.parse_args()
 
 
@@ -125,6 +128,88 @@ def run_precision(torch, api, inputs, pr, c_obs, precision, args, steps, warmup,
     del plan
     torch.cuda.empty_cache()
     return res
+
+
+def batch_workload(torch, np, api, inputs, reps):
+    """48 independent gradient evaluations (32 at 64^3, 16 at 128^3; seeded
+    phantoms, rho_f ~ U[5,15], k_f ~ U[0.01,0.5], 8/27/64 Gaussians, nt=16)
+    captured into one HIP graph and replayed."""
+    dev = torch.device("cuda:0")
+    items = []
+    groups = ((64, 32, 0), (128, 16, 32))
+    g_of = (2, 3, 4)
+    for n, nb, seed0 in groups:
+        probs = []
+        for s in range(nb):
+            seed = seed0 + s
+            pr = inputs.problem(n, g_of[seed % 3], seed, nt=16)
+            probs.append(pr)
+        npmax = max(q.p.size for q in probs)
+        cen = np.zeros((nb, npmax, 3))
+        p = np.zeros((nb, npmax))
+        for b, q in enumerate(probs):  # pad to a common basis size with p = 0
+            cen[b, :q.p.size] = q.centres
+            cen[b, q.p.size:] = q.centres[0]
+            p[b, :q.p.size] = q.p
+        plan = api.Plan(n, 16, cen, probs[0].sigma, rtol=1e-8, precision="fp32", batch=nb,
+                        ckpt_stride=4)
+        m = torch.tensor(np.stack([q.m for q in probs]), dtype=torch.float32, device=dev)
+        rho = [q.rho_f for q in probs]
+        kf = [q.k_f for q in probs]
+        pobs = np.stack([np.pad(inputs.perturbed_p(q.p, seed0 + b), (0, npmax - q.p.size))
+                         for b, q in enumerate(probs)])
+        cobs = (plan.forward(pobs, rho, kf, m) > 0.5).to(torch.float32)
+        plan.forward(p, rho, kf, m)
+        plan.adjoint_misfit(cobs)  # eager gradient: sizes the graph's PCG budget
+        items.append((plan, p, rho, kf, m, cobs))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t_eager = 0.0
+    for plan, p, rho, kf, m, cobs in items:
+        plan.forward(p, rho, kf, m)
+        plan.adjoint_misfit(cobs)
+    torch.cuda.synchronize()
+    t_eager = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    bg = api.BatchGraph(items)
+    t_capture = time.perf_counter() - t0
+    bg.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        bg.launch()
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / reps
+    status = [pl.stats().status_bits for pl in bg.plans]
+    return {"problems": 48, "workload": "32 x 64^3 + 16 x 128^3, nt=16, FP32-mixed, ckpt 4",
+            "graph_s_per_batch": t_graph, "graph_gradients_per_s": 48.0 / t_graph,
+            "eager_s_per_batch": t_eager, "eager_gradients_per_s": 48.0 / t_eager,
+            "capture_s": t_capture, "status_bits": status, "replays": reps}
+
+
+def hvp_workload(torch, api, inputs, pr, args):
+    """Gauss-Newton Hessian products at 256^3: 8 directions in p-space
+    (dim 64) batched, FP32-mixed, about the benchmark trajectory."""
+    dev = torch.device("cuda:0")
+    plan = api.Plan(pr.n, pr.nt, pr.centres, pr.sigma, T=pr.T, rtol=args.rtol,
+                    ckpt_stride=args.ckpt, precision="fp32", max_hvp_dirs=8)
+    m = torch.tensor(pr.m, dtype=torch.float32, device=dev)
+    plan.forward(pr.p, pr.rho_f, pr.k_f, m)
+    V = torch.tensor(inputs.hvp_directions(8, pr.p.size, args.seed), dtype=torch.float64,
+                     device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    HV = plan.hessvec(V)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    st = plan.stats()
+    Hm = (V @ HV.T).cpu().numpy()
+    sym = float(abs(Hm - Hm.T).max() / max(abs(Hm).max(), 1e-300))
+    del plan
+    torch.cuda.empty_cache()
+    return {"directions": 8, "seconds": t, "hvp_per_s": 8.0 / t,
+            "pcg_its": st.pcg_its_total, "solves": st.solves,
+            "symmetry_rel_err": sym, "status_bits": st.status_bits}
 
 
 def cpu_baseline(pr, res32):
@@ -249,6 +334,10 @@ def main():
             },
             "pcg_its_forward": r64["pcg_its_forward"], "pcg_its_adjoint": r64["pcg_its_adjoint"],
         }
+    if not args.no_batch:
+        out["batch"] = batch_workload(torch, np, api, inputs, args.batch_reps)
+    if not args.no_hvp:
+        out["hessvec"] = hvp_workload(torch, api, inputs, pr, args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(pr, r32)
     print(json.dumps(out), flush=True)

@@ -132,6 +132,16 @@ tg_status tg_adjoint_misfit(tg_plan* plan, const void* d_cobs, double* d_J, doub
 tg_status tg_hessvec_gn(tg_plan* plan, int ndir, const double* d_V, double* d_HV,
                         void* stream);
 
+/* Launch schedule of the transform passes (performance knobs only; results
+ * are identical up to the summation order of the FP64 partial sums).
+ * pencils: 8, 16 or 32 pencils per x/y-pass workgroup; z_waves: 1, 2 or 4
+ * waves per z-pass workgroup; slabs: 1, 2, 4 or 8 x-plane slabs over which
+ * the y-z-y pass chain of the diffusion operator runs slab by slab; 0
+ * selects the default.  Requires a bound plan.  Errors: TG_ERR_ARG for
+ * unsupported values. */
+tg_status tg_plan_set_schedule(tg_plan* plan, int pencils, int z_waves, int slabs);
+tg_status tg_plan_get_schedule(const tg_plan* plan, int* pencils, int* z_waves, int* slabs);
+
 /* PCG statistics of the last call (synchronizes the plan's last stream). */
 tg_status tg_stats(tg_plan* plan, tg_solve_stats* out);
 
@@ -148,6 +158,36 @@ tg_status tg_kernel_timer(tg_plan* plan, int kernel_id);
  * launches moved (launches that did work x fields read and written). */
 tg_status tg_kernel_timer_read(tg_plan* plan, double* total_ms, long long* launches,
                                double* work_bytes);
+
+/* Batched gradient evaluation as one replayable HIP graph (SURVEY-style
+ * "many problems in one launch"): for each plan, forward + misfit + adjoint
+ * (tg_forward then tg_adjoint_misfit) on that plan's batch of problems, all
+ * captured on `stream` into one graph.  Inside the graph every PCG solve
+ * runs a fixed, predicated iteration budget (kernels of converged problems
+ * return at once): pcg_budget, or if 0 the plan's largest per-solve count
+ * of its last eager forward/gradient + 25% + 4 (TG_ERR_STATE if there was
+ * none).  A solve that needs more is flagged TG_ERR_NOT_CONVERGED in
+ * tg_stats after the launch.  The io pointers are baked into the graph and
+ * must stay valid; their contents may change between launches. */
+typedef struct tg_batch tg_batch;
+typedef struct tg_batch_io {
+  const double* d_p;      /* [B][n_p] */
+  const double* d_rho_f;  /* [B] */
+  const double* d_k_f;    /* [B] */
+  const void* d_m;        /* [B][n^3] */
+  void* d_cT;             /* [B][n^3] out */
+  const void* d_cobs;     /* [B][n^3] */
+  double* d_J;            /* [B] out */
+  double* d_gp;           /* [B][n_p] out */
+  double* d_grho;         /* [B] out */
+  double* d_gkf;          /* [B] out */
+} tg_batch_io;
+
+tg_status tg_batch_capture(int nplans, tg_plan* const* plans, const tg_batch_io* io,
+                           int pcg_budget, void* stream, tg_batch** out);
+/* Replay the captured graph on `stream` (asynchronous). */
+tg_status tg_batch_launch(tg_batch* batch, void* stream);
+void tg_batch_destroy(tg_batch* batch);
 
 const char* tg_status_string(tg_status s);
 void tg_plan_destroy(tg_plan* plan);

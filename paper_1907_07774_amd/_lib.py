@@ -26,7 +26,8 @@ EXPORTS = (
     "tg_plan_create", "tg_plan_workspace_bytes", "tg_plan_bind", "tg_forward",
     "tg_vjp", "tg_adjoint_misfit", "tg_hessvec_gn", "tg_stats",
     "tg_status_string", "tg_plan_destroy", "tg_version", "tg_kernel_timer",
-    "tg_kernel_timer_read",
+    "tg_kernel_timer_read", "tg_plan_set_schedule", "tg_plan_get_schedule",
+    "tg_batch_capture", "tg_batch_launch", "tg_batch_destroy",
 )
 
 
@@ -37,6 +38,11 @@ class TgDesc(C.Structure):
         ("pcg_rtol", C.c_double), ("pcg_maxit", C.c_int), ("ckpt_stride", C.c_int),
         ("prec", C.c_int), ("batch", C.c_int), ("max_hvp_dirs", C.c_int),
     ]
+
+
+class TgBatchIo(C.Structure):
+    _fields_ = [(name, C.c_void_p) for name in (
+        "d_p", "d_rho_f", "d_k_f", "d_m", "d_cT", "d_cobs", "d_J", "d_gp", "d_grho", "d_gkf")]
 
 
 class TgSolveStats(C.Structure):
@@ -80,9 +86,18 @@ def lib():
     L.tg_version.restype = C.c_int
     L.tg_kernel_timer.argtypes = [vp, C.c_int]
     L.tg_kernel_timer_read.argtypes = [vp, dp, C.POINTER(C.c_longlong), dp]
+    L.tg_batch_capture.argtypes = [C.c_int, C.POINTER(vp), C.POINTER(TgBatchIo), C.c_int, vp,
+                                   C.POINTER(vp)]
+    L.tg_batch_launch.argtypes = [vp, vp]
+    L.tg_batch_destroy.argtypes = [vp]
+    L.tg_batch_destroy.restype = None
+    L.tg_plan_set_schedule.argtypes = [vp, C.c_int, C.c_int, C.c_int]
+    L.tg_plan_get_schedule.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                       C.POINTER(C.c_int)]
     for name in ("tg_plan_create", "tg_plan_workspace_bytes", "tg_plan_bind", "tg_forward",
                  "tg_vjp", "tg_adjoint_misfit", "tg_hessvec_gn", "tg_stats",
-                 "tg_kernel_timer", "tg_kernel_timer_read"):
+                 "tg_kernel_timer", "tg_kernel_timer_read", "tg_plan_set_schedule",
+                 "tg_plan_get_schedule", "tg_batch_capture", "tg_batch_launch"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L

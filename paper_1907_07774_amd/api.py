@@ -43,7 +43,7 @@ class Plan:
     def __init__(self, n: int, nt: int, centres, sigma: float, T: float = 1.0,
                  rtol: float = 1e-8, maxit: int = 1000, ckpt_stride: int = 0,
                  precision: str = "fp64", batch: int = 1, max_hvp_dirs: int = 0,
-                 device: str | torch.device = "cuda:0"):
+                 device: str | torch.device = "cuda:0", schedule=None):
         L = _lib.lib()
         cen = np.asarray(centres, dtype=np.float64)
         if cen.ndim == 2:
@@ -70,6 +70,7 @@ class Plan:
         _lib.check(L.tg_plan_workspace_bytes(h, C.byref(nbytes)), "tg_plan_workspace_bytes")
         self.workspace_bytes = int(nbytes.value)
         self._ws = None
+        self._schedule = schedule
         self._keep = ()
         self.generation = 0
 
@@ -83,6 +84,14 @@ class Plan:
             self._ws = ws
             _lib.check(_lib.lib().tg_plan_bind(self._h, C.c_void_p(ws.data_ptr() + off),
                                                 self.workspace_bytes), "tg_plan_bind")
+            if self._schedule is not None:
+                self.set_schedule(*self._schedule)
+            else:
+                from . import autotune
+                sch = autotune.lookup(autotune.gpu_arch(self.device), self.n, self.precision,
+                                      self.batch)
+                if sch is not None:
+                    self.set_schedule(*sch)
 
     def _stream(self):
         return C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
@@ -167,6 +176,22 @@ class Plan:
         return Stats(s.solves, s.pcg_its_total, s.pcg_its_max, s.status_bits,
                      s.worst_rel_residual)
 
+    def set_schedule(self, pencils: int = 0, z_waves: int = 0, slabs: int = 0):
+        """Choose the transform launch schedule (0 = default)."""
+        if self._ws is None:
+            self._schedule = (int(pencils), int(z_waves), int(slabs))
+            self._bind()
+            return
+        _lib.check(_lib.lib().tg_plan_set_schedule(self._h, int(pencils), int(z_waves),
+                                                    int(slabs)), "tg_plan_set_schedule")
+
+    def get_schedule(self):
+        self._bind()
+        a, b, c = C.c_int(), C.c_int(), C.c_int()
+        _lib.check(_lib.lib().tg_plan_get_schedule(self._h, C.byref(a), C.byref(b), C.byref(c)),
+                   "tg_plan_get_schedule")
+        return a.value, b.value, c.value
+
     KERNELS = {"x_inv_grad": 1, "y_inv_grad": 2, "z_matvec": 3, "y_fwd_div": 4,
                "x_fwd_div": 5, "pcg_update": 6}
 
@@ -224,3 +249,91 @@ class TumorSolve(torch.autograd.Function):
         p, rho, kf, _ = ctx.saved_tensors
         return (gp.view_as(p).to(p.dtype), gr.reshape(rho.shape).to(rho.dtype),
                 gk.reshape(kf.shape).to(kf.dtype), None, None)
+
+
+class BatchGraph:
+    """Gradient evaluations (forward + misfit + adjoint) of several plans
+    captured into one HIP graph and replayed with one launch.
+
+    items: list of (plan, p, rho_f, k_f, m, c_obs) with per-plan batched
+    inputs.  Each plan needs one eager gradient before capture (it sizes the
+    fixed PCG iteration budget) unless ``pcg_budget`` is given.  Inputs are
+    copied into buffers owned by this object; ``update`` rewrites them in
+    place between launches.
+    """
+
+    def __init__(self, items, pcg_budget: int = 0):
+        self.plans = [it[0] for it in items]
+        dev = self.plans[0].device
+        self.device = dev
+        self.stream = torch.cuda.Stream(device=dev)
+        self._bufs = []
+        ios = (_lib.TgBatchIo * len(items))()
+        for i, (plan, p, rho, kf, m, cobs) in enumerate(items):
+            plan._bind()
+            b = {
+                "p": plan._vec(p, plan.batch * plan.n_p, "p").clone(),
+                "rho": plan._vec(rho, plan.batch, "rho_f").clone(),
+                "kf": plan._vec(kf, plan.batch, "k_f").clone(),
+                "m": plan._field(m, "m").clone(),
+                "cobs": plan._field(cobs, "c_obs").clone(),
+            }
+            b["cT"] = torch.empty_like(b["m"])
+            b["J"] = torch.empty(plan.batch, dtype=torch.float64, device=dev)
+            b["gp"] = torch.empty(plan.batch * plan.n_p, dtype=torch.float64, device=dev)
+            b["grho"] = torch.empty(plan.batch, dtype=torch.float64, device=dev)
+            b["gkf"] = torch.empty(plan.batch, dtype=torch.float64, device=dev)
+            for f, k in (("d_p", "p"), ("d_rho_f", "rho"), ("d_k_f", "kf"), ("d_m", "m"),
+                         ("d_cT", "cT"), ("d_cobs", "cobs"), ("d_J", "J"), ("d_gp", "gp"),
+                         ("d_grho", "grho"), ("d_gkf", "gkf")):
+                setattr(ios[i], f, b[k].data_ptr())
+            self._bufs.append(b)
+        handles = (C.c_void_p * len(items))(*[pl._h.value for pl in self.plans])
+        h = C.c_void_p()
+        torch.cuda.synchronize(dev)
+        _lib.check(_lib.lib().tg_batch_capture(len(items), handles, ios, int(pcg_budget),
+                                               C.c_void_p(self.stream.cuda_stream), C.byref(h)),
+                   "tg_batch_capture")
+        self._h = h
+        for pl, b in zip(self.plans, self._bufs):
+            pl._keep = (b["p"], b["rho"], b["kf"], b["m"], b["cT"])
+            pl.generation += 1
+
+    def update(self, i, p=None, rho_f=None, k_f=None, m=None, c_obs=None):
+        b, pl = self._bufs[i], self.plans[i]
+        if p is not None:
+            b["p"].copy_(pl._vec(p, pl.batch * pl.n_p, "p"))
+        if rho_f is not None:
+            b["rho"].copy_(pl._vec(rho_f, pl.batch, "rho_f"))
+        if k_f is not None:
+            b["kf"].copy_(pl._vec(k_f, pl.batch, "k_f"))
+        if m is not None:
+            b["m"].copy_(pl._field(m, "m"))
+        if c_obs is not None:
+            b["cobs"].copy_(pl._field(c_obs, "c_obs"))
+
+    def launch(self):
+        """Replay the graph on this object's stream, ordered after the
+        current stream's prior work; the current stream waits for it."""
+        cur = torch.cuda.current_stream(self.device)
+        self.stream.wait_stream(cur)
+        _lib.check(_lib.lib().tg_batch_launch(self._h, C.c_void_p(self.stream.cuda_stream)),
+                   "tg_batch_launch")
+        cur.wait_stream(self.stream)
+
+    def results(self):
+        """[(J, g_p, g_rho, g_kf)] per plan (device tensors, batched)."""
+        out = []
+        for pl, b in zip(self.plans, self._bufs):
+            out.append((b["J"], b["gp"].view(pl.batch, pl.n_p), b["grho"], b["gkf"]))
+        return out
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                torch.cuda.synchronize(self.device)
+                _lib.lib().tg_batch_destroy(h)
+            except Exception:
+                pass
+            self._h = None

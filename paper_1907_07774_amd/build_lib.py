@@ -23,15 +23,15 @@ DEV_FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC"]
 
-UNITS = [
-    ("tg_solver_f32.hip", DEV_FLAGS),
-    ("tg_solver_f64.hip", DEV_FLAGS),
-    ("tg_api.cpp", HOST_FLAGS),
-]
+GRIDS = (8, 16, 32, 64, 128, 256)
+# one translation unit per (precision, grid size), plus the host layers
+UNITS = ([("tg_inst.hip", DEV_FLAGS + [f"-DTG_FP64={p}", f"-DTG_N={n}"], f"tg_inst_{p}_{n}")
+          for p in (0, 1) for n in GRIDS]
+         + [("tg_dispatch.cpp", HOST_FLAGS, "tg_dispatch"), ("tg_api.cpp", HOST_FLAGS, "tg_api")])
 
 
-def _compile(src: str, flags: list[str]) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+def _compile(src: str, flags: list[str], stem: str) -> str:
+    obj = os.path.join(BUILD, stem + ".o")
     cmd = [HIPCC, *flags, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -41,7 +41,8 @@ def _compile(src: str, flags: list[str]) -> str:
 
 def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=len(UNITS)) as ex:
+    workers = max(1, min(len(UNITS), os.cpu_count() or 1, 16))
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
         objs = list(ex.map(lambda u: _compile(*u), UNITS))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]

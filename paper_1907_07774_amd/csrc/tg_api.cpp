@@ -7,6 +7,8 @@
 #include <cstring>
 #include <memory>
 #include <mutex>
+#include <set>
+#include <tuple>
 #include <vector>
 
 #include "../../include/tumorgrad.h"
@@ -72,18 +74,18 @@ tg_status from_bits(int bits) {
 }
 
 std::mutex g_tw_mu;
-std::vector<int> g_tw_done;  // per device: bit 1 = f32 table, bit 2 = f64 table
+std::set<std::tuple<int, int, int>> g_tw_done;  // (device, fp64, n) tables filled
 
-hipError_t ensure_twiddles(tg_precision prec) {
+hipError_t ensure_twiddles(tg_precision prec, int n) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
+  const int fp64 = prec == TG_FP64 ? 1 : 0;
   std::lock_guard<std::mutex> lk(g_tw_mu);
-  if ((int)g_tw_done.size() <= dev) g_tw_done.resize(dev + 1, 0);
-  const int bit = prec == TG_FP64 ? 2 : 1;
-  if (g_tw_done[dev] & bit) return hipSuccess;
-  e = prec == TG_FP64 ? tg::init_twiddles_f64() : tg::init_twiddles_f32();
-  if (e == hipSuccess) g_tw_done[dev] |= bit;
+  const auto key = std::make_tuple(dev, fp64, n);
+  if (g_tw_done.count(key)) return hipSuccess;
+  e = tg::init_twiddles(fp64, n);
+  if (e == hipSuccess) g_tw_done.insert(key);
   return e;
 }
 
@@ -154,15 +156,14 @@ tg_status tg_plan_bind(tg_plan* plan, void* d_ws, size_t bytes) {
   if (plan == nullptr) return TG_ERR_ARG;
   if (d_ws == nullptr || bytes < plan->ws_bytes || ((uintptr_t)d_ws % ALIGN) != 0)
     return TG_ERR_WORKSPACE;
-  hipError_t e = ensure_twiddles(plan->d.prec);
+  hipError_t e = ensure_twiddles(plan->d.prec, plan->d.n);
   if (e != hipSuccess) return TG_ERR_HIP;
   plan->ws = d_ws;
   layout(*plan, (char*)d_ws, &plan->w);
   e = hipMemcpy(plan->w.centres, plan->centres.data(), plan->centres.size() * sizeof(double),
                 hipMemcpyHostToDevice);
   if (e != hipSuccess) return TG_ERR_HIP;
-  plan->solver.reset(plan->d.prec == TG_FP64 ? tg::make_solver_f64(plan->dims, plan->w)
-                                              : tg::make_solver_f32(plan->dims, plan->w));
+  plan->solver.reset(tg::make_solver(plan->d.prec == TG_FP64 ? 1 : 0, plan->dims, plan->w));
   if (!plan->solver) return TG_ERR_ARG;
   plan->have_traj = false;
   return TG_OK;
@@ -247,6 +248,101 @@ tg_status tg_kernel_timer_read(tg_plan* plan, double* total_ms, long long* launc
     return TG_ERR_ARG;
   if (!plan->solver) return TG_ERR_WORKSPACE;
   return from_hip(plan->solver->timer_read(total_ms, launches, work_bytes));
+}
+
+tg_status tg_plan_set_schedule(tg_plan* plan, int pencils, int z_waves, int slabs) {
+  if (plan == nullptr) return TG_ERR_ARG;
+  if (!plan->solver) return TG_ERR_WORKSPACE;
+  if (!(pencils == 0 || pencils == 8 || pencils == 16 || pencils == 32)) return TG_ERR_ARG;
+  if (!(z_waves == 0 || z_waves == 1 || z_waves == 2 || z_waves == 4)) return TG_ERR_ARG;
+  if (!(slabs == 0 || slabs == 1 || slabs == 2 || slabs == 4 || slabs == 8)) return TG_ERR_ARG;
+  if (!plan->solver->set_schedule(pencils, z_waves, slabs)) return TG_ERR_ARG;
+  return TG_OK;
+}
+
+tg_status tg_plan_get_schedule(const tg_plan* plan, int* pencils, int* z_waves, int* slabs) {
+  if (plan == nullptr || pencils == nullptr || z_waves == nullptr || slabs == nullptr)
+    return TG_ERR_ARG;
+  if (!plan->solver) return TG_ERR_WORKSPACE;
+  plan->solver->get_schedule(pencils, z_waves, slabs);
+  return TG_OK;
+}
+
+struct tg_batch {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<tg_plan*> plans;
+};
+
+tg_status tg_batch_capture(int nplans, tg_plan* const* plans, const tg_batch_io* io,
+                           int pcg_budget, void* stream, tg_batch** out) {
+  if (out == nullptr) return TG_ERR_ARG;
+  *out = nullptr;
+  if (nplans < 1 || plans == nullptr || io == nullptr || pcg_budget < 0) return TG_ERR_ARG;
+  std::vector<int> budgets(nplans);
+  for (int i = 0; i < nplans; ++i) {
+    tg_plan* p = plans[i];
+    const tg_batch_io& b = io[i];
+    if (p == nullptr || b.d_p == nullptr || b.d_rho_f == nullptr || b.d_k_f == nullptr ||
+        b.d_m == nullptr || b.d_cT == nullptr || b.d_cobs == nullptr || b.d_J == nullptr ||
+        b.d_gp == nullptr || b.d_grho == nullptr || b.d_gkf == nullptr)
+      return TG_ERR_ARG;
+    if (!p->solver) return TG_ERR_WORKSPACE;
+    int its = pcg_budget;
+    if (its == 0) {
+      const int seen = p->solver->its_max_last_call();
+      if (seen <= 0) return TG_ERR_STATE;  // no eager gradient to size the budget from
+      its = seen + seen / 4 + 4;
+    }
+    budgets[i] = its;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return TG_ERR_HIP;
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < nplans && e == hipSuccess; ++i) {
+    tg_plan* p = plans[i];
+    const tg_batch_io& b = io[i];
+    p->solver->set_graph_budget(budgets[i]);
+    e = p->solver->forward(b.d_p, b.d_rho_f, b.d_k_f, b.d_m, b.d_cT, st);
+    if (e == hipSuccess)
+      e = p->solver->vjp(nullptr, b.d_cobs, b.d_J, b.d_gp, b.d_grho, b.d_gkf, st);
+    p->solver->set_graph_budget(0);
+    p->last_stream = st;
+  }
+  hipGraph_t graph = nullptr;
+  hipError_t e2 = hipStreamEndCapture(st, &graph);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (graph) hipGraphDestroy(graph);
+    return TG_ERR_HIP;
+  }
+  tg_batch* bt = new tg_batch;
+  bt->graph = graph;
+  bt->plans.assign(plans, plans + nplans);
+  if (hipGraphInstantiate(&bt->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    hipGraphDestroy(graph);
+    delete bt;
+    return TG_ERR_HIP;
+  }
+  for (tg_plan* p : bt->plans) p->have_traj = false;  // valid after the first launch
+  *out = bt;
+  return TG_OK;
+}
+
+tg_status tg_batch_launch(tg_batch* batch, void* stream) {
+  if (batch == nullptr || batch->exec == nullptr) return TG_ERR_ARG;
+  if (hipGraphLaunch(batch->exec, (hipStream_t)stream) != hipSuccess) return TG_ERR_HIP;
+  for (tg_plan* p : batch->plans) {
+    p->have_traj = true;
+    p->last_stream = (hipStream_t)stream;
+  }
+  return TG_OK;
+}
+
+void tg_batch_destroy(tg_batch* batch) {
+  if (batch == nullptr) return;
+  if (batch->exec) hipGraphExecDestroy(batch->exec);
+  if (batch->graph) hipGraphDestroy(batch->graph);
+  delete batch;
 }
 
 void tg_plan_destroy(tg_plan* plan) { delete plan; }

@@ -37,7 +37,7 @@ struct ProbScalars {
 enum : int { STAT_NOT_CONVERGED = 1, STAT_BREAKDOWN = 2, STAT_NONFINITE = 4 };
 
 constexpr int NSLOT = 4;      // simultaneous partial sums per reducing kernel
-constexpr int MAXBLK = 2048;  // max workgroups of a reducing kernel per problem
+constexpr int MAXBLK = 8192;  // max workgroups of a reducing kernel per problem
 
 struct SolverDims {
   int n, nt, n_p, batch, dirs, s, nseg;
@@ -82,6 +82,16 @@ class ISolver {
   // Event timing of one kernel of the PCG iteration (KT_* id; KT_NONE off).
   virtual hipError_t timer_enable(int id) = 0;
   virtual hipError_t timer_read(double* ms, long long* launches, double* work_bytes) = 0;
+  // Transform tile shapes: pencils per x/y workgroup (8, 16, 32), waves
+  // per z workgroup (1, 2, 4) and x slabs of the y-z-y pass chain (1, 2,
+  // 4, 8); 0 = default.  False if not available.
+  virtual bool set_schedule(int C, int zwaves, int slabs) = 0;
+  // Graph-capture mode: every PCG solve runs exactly `budget` predicated
+  // iterations with no host synchronization (0 = eager, adaptive).
+  virtual void set_graph_budget(int budget) = 0;
+  // Largest PCG iteration count of one solve seen since the last forward.
+  virtual int its_max_last_call() const = 0;
+  virtual void get_schedule(int* C, int* zwaves, int* slabs) const = 0;
 };
 
 enum KernelId : int {
@@ -96,9 +106,10 @@ enum KernelId : int {
 
 // Phi^T partial-block count for grid size n (workspace sizing).
 int phi_blocks_for(int n);
-ISolver* make_solver_f32(const SolverDims& d, const Workspace& w);
-ISolver* make_solver_f64(const SolverDims& d, const Workspace& w);
-hipError_t init_twiddles_f32();
-hipError_t init_twiddles_f64();
+// Solver for (precision, n); nullptr if n is not supported.  Each
+// instantiation lives in its own translation unit with its own twiddle
+// table, filled by init_twiddles for the current device.
+ISolver* make_solver(int fp64, const SolverDims& d, const Workspace& w);
+hipError_t init_twiddles(int fp64, int n);
 
 }  // namespace tg

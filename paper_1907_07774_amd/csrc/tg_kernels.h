@@ -99,14 +99,15 @@ struct SP {
   }
 };
 
-#define SP_SETUP(AXV)                                                   \
+#define SP_SETUP(AXV) SP_SETUP_OFF(AXV, 0)
+#define SP_SETUP_OFF(AXV, OFF)                                          \
   using S = SP<T, N, C, AXV>;                                           \
   constexpr int E = S::E, TT = S::TT, NH = S::NH;                       \
   (void)NH;                                                             \
   __shared__ cx<T> lds[(S::TT > 1) ? N * C : 1];                        \
   const int b = blockIdx.y;                                             \
   const int col = threadIdx.x % C, t = threadIdx.x / C;                 \
-  const int gc = blockIdx.x * C + col;                                  \
+  const int gc = ((int)blockIdx.x + (OFF)) * C + col;                   \
   const long long base = (long long)b * S::SPEC + S::colbase(gc);
 
 // ---- x pass, inverse, gradient prologue of the diffusion matvec.
@@ -160,8 +161,8 @@ k_x_inv_grad(cx<T>* __restrict__ P, const cx<T>* __restrict__ Rr, cx<T>* __restr
 template <typename T, int N, int C>
 __global__ void __launch_bounds__((SP<T, N, C, 1>::NT))
 k_y_inv_grad(cx<T>* __restrict__ U1, cx<T>* __restrict__ U2, cx<T>* __restrict__ V3,
-             const ProbScalars* __restrict__ sc, int pred) {
-  SP_SETUP(1)
+             const ProbScalars* __restrict__ sc, int pred, int blk0) {
+  SP_SETUP_OFF(1, blk0)
   if (pred && sc[b].done) return;
   cx<T> v[E], u[E], w[E];
 #pragma unroll
@@ -187,8 +188,8 @@ k_y_inv_grad(cx<T>* __restrict__ U1, cx<T>* __restrict__ U2, cx<T>* __restrict__
 template <typename T, int N, int C>
 __global__ void __launch_bounds__((SP<T, N, C, 1>::NT))
 k_y_fwd_div(cx<T>* __restrict__ H1, cx<T>* __restrict__ H2, const cx<T>* __restrict__ H3,
-            const ProbScalars* __restrict__ sc, int pred) {
-  SP_SETUP(1)
+            const ProbScalars* __restrict__ sc, int pred, int blk0) {
+  SP_SETUP_OFF(1, blk0)
   if (pred && sc[b].done) return;
   constexpr bool PRE = sizeof(T) == 4;
   cx<T> v[E], a[E], c[E];
@@ -382,17 +383,26 @@ k_x_fwd_state(const cx<T>* __restrict__ H, cx<T>* __restrict__ X, cx<T>* __restr
 // Rows (b, x, y) of n reals = n/2 complex.  RW rows per workgroup; thread
 // (t, row) holds complex positions t + TT e.  LDS row pitch L + TT spreads
 // the rows of a wave over the banks.
-template <typename T, int N>
+template <int N>
+struct ZDefaultRows {
+  static constexpr int L = N / 2;
+  static constexpr int TT = L / FftE<L>::value;
+  static constexpr int value = (TT * 64 <= 256) ? 64 : 256 / TT;
+};
+
+template <typename T, int N, int RW_ = ZDefaultRows<N>::value>
 struct ZP {
   static constexpr int L = N / 2;
   static constexpr int E = FftE<L>::value;
   static constexpr int TT = L / E;
-  static constexpr int RW = (TT * 64 <= 256) ? 64 : 256 / TT;
+  static constexpr int RW = RW_;
   static constexpr int NT = TT * RW;
   static constexpr int PITCH = L + TT;
   static constexpr int NBLK = N * N / RW;
   static constexpr long long SPEC = (long long)N * N * (N / 2);
   static constexpr long long REAL = (long long)N * N * N;
+  static_assert(N * N % RW == 0, "rows per block must divide the row count");
+  static_assert(64 % TT == 0, "a row must stay inside one wave");
 };
 
 // Mirror partner of the value held in register e of row-thread t:
@@ -476,7 +486,7 @@ __device__ __forceinline__ void r2c_row(cx<T> (&v)[E], cx<T>* lds, int t, int ro
 }
 
 #define ZP_SETUP                                                        \
-  using Z = ZP<T, N>;                                                   \
+  using Z = ZP<T, N, RW>;                                               \
   constexpr int E = Z::E, TT = Z::TT;                                   \
   __shared__ cx<T> lds[Z::RW * Z::PITCH];                               \
   const int b = blockIdx.y;                                             \
@@ -486,22 +496,23 @@ __device__ __forceinline__ void r2c_row(cx<T> (&v)[E], cx<T>* lds, int t, int ro
   (void)sbase;
 
 // ---- matvec core: for j = x, y, z: g_j = C2R(V_j) (V_z times i wz), times
-// m, R2C, (z: times i wz).  In place on V1..V3.  rev walks the rows from
+// m, R2C, (z: times i wz).  In place on V1..V3.  The launch covers the
+// blocks [blk0, blk0 + gridDim.x) (a slab of x planes); rev walks them from
 // the last to the first (the y pass before it ends at the last rows, whose
 // output is then still in the last-level cache).  FP32 loads all three
 // rows up front.
-template <typename T, int N>
-__global__ void __launch_bounds__((ZP<T, N>::NT))
+template <typename T, int N, int RW>
+__global__ void __launch_bounds__((ZP<T, N, RW>::NT))
 k_z_matvec(cx<T>* __restrict__ V1, cx<T>* __restrict__ V2, cx<T>* __restrict__ V3,
            const T* __restrict__ m, long long m_bs, const ProbScalars* __restrict__ sc, int pred,
-           int rev) {
-  using Z = ZP<T, N>;
+           int rev, int blk0) {
+  using Z = ZP<T, N, RW>;
   constexpr int E = Z::E, TT = Z::TT;
   __shared__ cx<T> lds[Z::RW * Z::PITCH];
   const int b = blockIdx.y;
   if (pred && sc[b].done) return;
   const int t = threadIdx.x % TT, row = threadIdx.x / TT;
-  const int bx = rev ? (int)gridDim.x - 1 - (int)blockIdx.x : (int)blockIdx.x;
+  const int bx = blk0 + (rev ? (int)gridDim.x - 1 - (int)blockIdx.x : (int)blockIdx.x);
   const long long grow = (long long)bx * Z::RW + row;
   const long long sbase = (long long)b * Z::SPEC + grow * Z::L;
   const cx<T>* mrow = reinterpret_cast<const cx<T>*>(m + b * m_bs + grow * N);
@@ -568,8 +579,8 @@ struct ZArgs {
   int want_grho;
 };
 
-template <typename T, int N, int MODE>
-__global__ void __launch_bounds__((ZP<T, N>::NT)) k_z_step(ZArgs a) {
+template <typename T, int N, int MODE, int RW>
+__global__ void __launch_bounds__((ZP<T, N, RW>::NT)) k_z_step(ZArgs a) {
   ZP_SETUP
   __shared__ double red[NSLOT * ((Z::NT + 63) / 64)];
   const long long roff = grow * N;  // real element offset of the row

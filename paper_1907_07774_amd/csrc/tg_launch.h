@@ -1,0 +1,166 @@
+// Launch tables: the transform passes exist in several tile shapes (pencils
+// per x/y workgroup, rows per z workgroup); a plan picks one of each at run
+// time (defaults or the autotuner's choice) without recompiling.
+#pragma once
+#include "tg_kernels.h"
+
+namespace tg {
+
+template <typename T, int N>
+struct Sched {
+  int C = 0;       // pencils per x/y workgroup
+  int RW = 0;      // rows per z workgroup
+  int sx_nblk = 0; // x-pass workgroups per problem (partial-sum count)
+  int z_nblk = 0;  // z-pass workgroups per problem (partial-sum count)
+  int sy_nblk = 0; // y-pass workgroups per problem
+  void (*x_inv_grad)(int mode, cx<T>* P, const cx<T>* R, cx<T>* U1, cx<T>* U2,
+                     const ProbScalars* sc, double tau, int pred, int nb, hipStream_t st) = nullptr;
+  // y-pass and z-pass launches over slab k of nslab (x-plane ranges)
+  void (*y_inv_grad)(cx<T>* U1, cx<T>* U2, cx<T>* V3, const ProbScalars* sc, int pred, int nb,
+                     int k, int nslab, hipStream_t st) = nullptr;
+  void (*y_fwd_div)(cx<T>* H1, cx<T>* H2, const cx<T>* H3, const ProbScalars* sc, int pred, int nb,
+                    int k, int nslab, hipStream_t st) = nullptr;
+  void (*x_fwd_div)(int mode, const cx<T>* W1, const cx<T>* W23, cx<T>* X, cx<T>* Q,
+                    const cx<T>* Sv, const ProbScalars* sc, double* part, double tau, int pred,
+                    int want_gk, int nb, hipStream_t st) = nullptr;
+  void (*x_inv)(const cx<T>* X, cx<T>* Y, int nb, hipStream_t st) = nullptr;
+  void (*y_plain)(bool inv, cx<T>* Y, cx<T>* Y2, int nb, hipStream_t st) = nullptr;
+  void (*x_fwd_state)(const cx<T>* H, cx<T>* X, cx<T>* U1, cx<T>* U2, cx<T>* S2, int nb,
+                      hipStream_t st) = nullptr;
+  void (*z_matvec)(cx<T>* V1, cx<T>* V2, cx<T>* V3, const T* m, long long m_bs,
+                   const ProbScalars* sc, int pred, int rev, int nb, int k, int nslab,
+                   hipStream_t st) = nullptr;
+  void (*z_step)(int mode, const ZArgs& a, int nb, hipStream_t st) = nullptr;
+};
+
+template <typename T, int N, int C>
+struct SLaunch {
+  using SX = SP<T, N, C, 0>;
+  using SY = SP<T, N, C, 1>;
+  static void x_inv_grad(int mode, cx<T>* P, const cx<T>* R, cx<T>* U1, cx<T>* U2,
+                         const ProbScalars* sc, double tau, int pred, int nb, hipStream_t st) {
+    if (mode == 1)
+      k_x_inv_grad<T, N, C, 1><<<dim3(SX::NBLK, nb), SX::NT, 0, st>>>(P, R, U1, U2, sc, tau, pred);
+    else
+      k_x_inv_grad<T, N, C, 0><<<dim3(SX::NBLK, nb), SX::NT, 0, st>>>(P, R, U1, U2, sc, tau, pred);
+  }
+  static void y_inv_grad(cx<T>* U1, cx<T>* U2, cx<T>* V3, const ProbScalars* sc, int pred, int nb,
+                         int k, int nslab, hipStream_t st) {
+    const int nbk = SY::NBLK / nslab;
+    k_y_inv_grad<T, N, C><<<dim3(nbk, nb), SY::NT, 0, st>>>(U1, U2, V3, sc, pred, k * nbk);
+  }
+  static void y_fwd_div(cx<T>* H1, cx<T>* H2, const cx<T>* H3, const ProbScalars* sc, int pred,
+                        int nb, int k, int nslab, hipStream_t st) {
+    const int nbk = SY::NBLK / nslab;
+    k_y_fwd_div<T, N, C><<<dim3(nbk, nb), SY::NT, 0, st>>>(H1, H2, H3, sc, pred, k * nbk);
+  }
+  static void x_fwd_div(int mode, const cx<T>* W1, const cx<T>* W23, cx<T>* X, cx<T>* Q,
+                        const cx<T>* Sv, const ProbScalars* sc, double* part, double tau, int pred,
+                        int want_gk, int nb, hipStream_t st) {
+    const dim3 g(SX::NBLK, nb);
+    switch (mode) {
+      case XM_PCG:
+        k_x_fwd_div<T, N, C, XM_PCG><<<g, SX::NT, 0, st>>>(W1, W23, X, Q, Sv, sc, part, tau, pred, want_gk);
+        break;
+      case XM_RHS_FWD:
+        k_x_fwd_div<T, N, C, XM_RHS_FWD><<<g, SX::NT, 0, st>>>(W1, W23, X, Q, Sv, sc, part, tau, pred, want_gk);
+        break;
+      case XM_RHS_ADJ:
+        k_x_fwd_div<T, N, C, XM_RHS_ADJ><<<g, SX::NT, 0, st>>>(W1, W23, X, Q, Sv, sc, part, tau, pred, want_gk);
+        break;
+      default:
+        k_x_fwd_div<T, N, C, XM_POST_ADJ><<<g, SX::NT, 0, st>>>(W1, W23, X, Q, Sv, sc, part, tau, pred, want_gk);
+        break;
+    }
+  }
+  static void x_inv(const cx<T>* X, cx<T>* Y, int nb, hipStream_t st) {
+    k_x_inv<T, N, C><<<dim3(SX::NBLK, nb), SX::NT, 0, st>>>(X, Y);
+  }
+  static void y_plain(bool inv, cx<T>* Y, cx<T>* Y2, int nb, hipStream_t st) {
+    if (inv)
+      k_y_plain<T, N, C, true><<<dim3(SY::NBLK, nb), SY::NT, 0, st>>>(Y, Y2);
+    else
+      k_y_plain<T, N, C, false><<<dim3(SY::NBLK, nb), SY::NT, 0, st>>>(Y, Y2);
+  }
+  static void x_fwd_state(const cx<T>* H, cx<T>* X, cx<T>* U1, cx<T>* U2, cx<T>* S2, int nb,
+                          hipStream_t st) {
+    k_x_fwd_state<T, N, C><<<dim3(SX::NBLK, nb), SX::NT, 0, st>>>(H, X, U1, U2, S2);
+  }
+  static void fill(Sched<T, N>& s) {
+    s.C = C;
+    s.sx_nblk = SX::NBLK;
+    s.sy_nblk = SY::NBLK;
+    s.x_inv_grad = &x_inv_grad;
+    s.y_inv_grad = &y_inv_grad;
+    s.y_fwd_div = &y_fwd_div;
+    s.x_fwd_div = &x_fwd_div;
+    s.x_inv = &x_inv;
+    s.y_plain = &y_plain;
+    s.x_fwd_state = &x_fwd_state;
+  }
+};
+
+template <typename T, int N, int RW>
+struct ZLaunch {
+  using Z = ZP<T, N, RW>;
+  static void z_matvec(cx<T>* V1, cx<T>* V2, cx<T>* V3, const T* m, long long m_bs,
+                       const ProbScalars* sc, int pred, int rev, int nb, int k, int nslab,
+                       hipStream_t st) {
+    const int nbk = Z::NBLK / nslab;
+    k_z_matvec<T, N, RW><<<dim3(nbk, nb), Z::NT, 0, st>>>(V1, V2, V3, m, m_bs, sc, pred, rev,
+                                                           k * nbk);
+  }
+  template <int MODE>
+  static void zs(const ZArgs& a, int nb, hipStream_t st) {
+    k_z_step<T, N, MODE, RW><<<dim3(Z::NBLK, nb), Z::NT, 0, st>>>(a);
+  }
+  static void z_step(int mode, const ZArgs& a, int nb, hipStream_t st) {
+    switch (mode) {
+      case ZS_FWD_FIRST: zs<ZS_FWD_FIRST>(a, nb, st); break;
+      case ZS_FWD: zs<ZS_FWD>(a, nb, st); break;
+      case ZS_FWD_LAST: zs<ZS_FWD_LAST>(a, nb, st); break;
+      case ZS_TAN_FIRST: zs<ZS_TAN_FIRST>(a, nb, st); break;
+      case ZS_TAN: zs<ZS_TAN>(a, nb, st); break;
+      case ZS_TAN_LAST: zs<ZS_TAN_LAST>(a, nb, st); break;
+      case ZS_ADJ_FIRST: zs<ZS_ADJ_FIRST>(a, nb, st); break;
+      case ZS_ADJ: zs<ZS_ADJ>(a, nb, st); break;
+      default: zs<ZS_ADJ_LAST>(a, nb, st); break;
+    }
+  }
+  static void fill(Sched<T, N>& s) {
+    s.RW = RW;
+    s.z_nblk = Z::NBLK;
+    s.z_matvec = &z_matvec;
+    s.z_step = &z_step;
+  }
+};
+
+// Candidate tile shapes.  Pencils per x/y workgroup: 8, 16, 32 (row
+// segments of 64..512 bytes).  Rows per z workgroup: one, two or four waves.
+template <typename T, int N>
+bool set_strided(Sched<T, N>& s, int C) {
+  switch (C) {
+    case 8: SLaunch<T, N, 8>::fill(s); return true;
+    case 16: SLaunch<T, N, 16>::fill(s); return true;
+    case 32: SLaunch<T, N, 32>::fill(s); return true;
+  }
+  return false;
+}
+
+template <typename T, int N>
+bool set_zrows(Sched<T, N>& s, int waves) {
+  constexpr int TT = ZP<T, N>::TT;
+  constexpr int r1 = 64 / TT;
+  switch (waves) {
+    case 1: ZLaunch<T, N, r1>::fill(s); return true;
+    case 2:
+      if constexpr (N * N >= 2 * r1) { ZLaunch<T, N, 2 * r1>::fill(s); return true; }
+      return false;
+    case 4:
+      if constexpr (N * N >= 4 * r1) { ZLaunch<T, N, 4 * r1>::fill(s); return true; }
+      return false;
+  }
+  return false;
+}
+
+}  // namespace tg

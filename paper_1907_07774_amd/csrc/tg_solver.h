@@ -15,7 +15,7 @@
 #include <cmath>
 #include <vector>
 
-#include "tg_kernels.h"
+#include "tg_launch.h"
 
 namespace tg {
 
@@ -28,10 +28,6 @@ namespace tg {
 
 template <typename T, int N>
 class Solver final : public ISolver {
-  static constexpr int C = sizeof(T) == 4 ? 32 : 16;  // pencils per x/y workgroup
-  using SX = SP<T, N, C, 0>;
-  using SY = SP<T, N, C, 1>;
-  using Z = ZP<T, N>;
   using W = PW<T, N>;
   using RPc = RP<T, N>;
   using PT = PhiT<T, N>;
@@ -56,6 +52,31 @@ class Solver final : public ISolver {
     h3_ = h * h * h;
     hsc_.resize(d.batch + d.dirs);
     its_est_ = 8;
+    set_schedule(0, 0, 0);
+  }
+
+  // Tile shapes of the transform passes; 0 picks the default.
+  bool set_schedule(int C, int zwaves, int slabs) override {
+    Sched<T, N> s;
+    if (C == 0) C = 16;
+    if (zwaves == 0) zwaves = 1;
+    if (slabs == 0) slabs = 1;
+    if (slabs != 1 && slabs != 2 && slabs != 4 && slabs != 8) return false;
+    if (!set_strided<T, N>(s, C)) return false;
+    if (!set_zrows<T, N>(s, zwaves)) {
+      if (!set_zrows<T, N>(s, 1)) return false;
+      zwaves = 1;
+    }
+    if (s.sy_nblk % slabs != 0 || s.z_nblk % slabs != 0) return false;
+    sch_ = s;
+    zwaves_ = zwaves;
+    nslab_ = slabs;
+    return true;
+  }
+  void get_schedule(int* C, int* zwaves, int* slabs) const override {
+    *C = sch_.C;
+    *zwaves = zwaves_;
+    *slabs = nslab_;
   }
 
   // ------------------------------------------------------------ forward
@@ -63,6 +84,7 @@ class Solver final : public ISolver {
                      void* cT, hipStream_t st) override {
     st_ = st;
     call_status_ = 0;
+    its_max_call_ = 0;
     m_ = (const T*)m;
     cT_ = (T*)cT;
     Ctx c = prim();
@@ -166,6 +188,15 @@ class Solver final : public ISolver {
 
   int last_status() const override { return call_status_; }
 
+  void set_graph_budget(int budget) override {
+    if (budget > 0 && tm_id_ != KT_NONE) {
+      timer_flush();
+      tm_id_ = KT_NONE;
+    }
+    graph_budget_ = budget;
+  }
+  int its_max_last_call() const override { return its_max_call_; }
+
   hipError_t read_stats(CallStats* out, hipStream_t st) override {
     const int nb = stat_nb_;
     if (stat_sc_ == nullptr) {
@@ -232,54 +263,60 @@ class Solver final : public ISolver {
 
   template <int MODE>
   void launch_z(const ZArgs& a, int nb) {
-    k_z_step<T, N, MODE><<<dim3(Z::NBLK, nb), Z::NT, 0, st_>>>(a);
+    sch_.z_step(MODE, a, nb, st_);
   }
 
   // spectral X -> T1 rows ready for a z pass (x then y inverse, 1/n^3)
   hipError_t inv_xy(const Ctx& c, cx<T>* X, cx<T>* Y) {
-    k_x_inv<T, N, C><<<dim3(SX::NBLK, c.nb), SX::NT, 0, st_>>>(X, Y);
+    sch_.x_inv(X, Y, c.nb, st_);
     TG_LAUNCH_CHECK();
-    k_y_plain<T, N, C, true><<<dim3(SY::NBLK, c.nb), SY::NT, 0, st_>>>(Y, nullptr);
+    sch_.y_plain(true, Y, nullptr, c.nb, st_);
     TG_LAUNCH_CHECK();
     return hipSuccess;
   }
 
-  // matvec tail: U1 = T?, U2 = T? given; produces W1, W23 in place, V3 in V3buf
+  // matvec middle (y inverse, z, y forward) on U1, U2 (V3 scratch); the
+  // three passes run slab by slab over nslab x-plane ranges so each slab's
+  // intermediates can stay in the last-level cache between passes.
   void matvec_mid(const Ctx& c, cx<T>* U1, cx<T>* U2, cx<T>* V3, int pred) {
     const int work = pred ? 0 : c.nb;
-    timed(KT_Y_INV_GRAD, work, [&] {
-      k_y_inv_grad<T, N, C><<<dim3(SY::NBLK, c.nb), SY::NT, 0, st_>>>(U1, U2, V3, c.sc, pred);
-    });
-    timed(KT_Z_MATVEC, work, [&] {
-      k_z_matvec<T, N><<<dim3(Z::NBLK, c.nb), Z::NT, 0, st_>>>(U1, U2, V3, c.m, c.m_bs, c.sc, pred,
-                                                               1);
-    });
-    timed(KT_Y_FWD_DIV, work, [&] {
-      k_y_fwd_div<T, N, C><<<dim3(SY::NBLK, c.nb), SY::NT, 0, st_>>>(U1, U2, V3, c.sc, pred);
-    });
+    const int ns = nslab_;
+    for (int k = 0; k < ns; ++k) {
+      timed(KT_Y_INV_GRAD, k == 0 ? work : 0, [&] {
+        sch_.y_inv_grad(U1, U2, V3, c.sc, pred, c.nb, k, ns, st_);
+      });
+      timed(KT_Z_MATVEC, k == 0 ? work : 0, [&] {
+        sch_.z_matvec(U1, U2, V3, c.m, c.m_bs, c.sc, pred, 1, c.nb, k, ns, st_);
+      });
+      timed(KT_Y_FWD_DIV, k == 0 ? work : 0, [&] {
+        sch_.y_fwd_div(U1, U2, V3, c.sc, pred, c.nb, k, ns, st_);
+      });
+    }
   }
 
   // After a boundary z kernel left the step's real-to-spectral rows in T1
   // (and S for the adjoint): finish the transform into X, run the right-
   // hand-side matvec and the PCG solve.
   hipError_t step_solve(const Ctx& c, bool adj) {
-    k_y_plain<T, N, C, false><<<dim3(SY::NBLK, c.nb), SY::NT, 0, st_>>>(c.T1, adj ? c.S : nullptr);
+    sch_.y_plain(false, c.T1, adj ? c.S : nullptr, c.nb, st_);
     TG_LAUNCH_CHECK();
-    k_x_fwd_state<T, N, C><<<dim3(SX::NBLK, c.nb), SX::NT, 0, st_>>>(c.T1, c.X, c.T2, c.T3,
-                                                                     adj ? c.S : nullptr);
+    sch_.x_fwd_state(c.T1, c.X, c.T2, c.T3, adj ? c.S : nullptr, c.nb, st_);
     TG_LAUNCH_CHECK();
     matvec_mid(c, c.T2, c.T3, c.T1, 0);
     TG_LAUNCH_CHECK();
-    if (adj)
-      k_x_fwd_div<T, N, C, XM_RHS_ADJ><<<dim3(SX::NBLK, c.nb), SX::NT, 0, st_>>>(
-          c.T2, c.T3, c.X, c.R, nullptr, c.sc, c.part, tau_, 0, 0);
-    else
-      k_x_fwd_div<T, N, C, XM_RHS_FWD><<<dim3(SX::NBLK, c.nb), SX::NT, 0, st_>>>(
-          c.T2, c.T3, c.X, c.R, nullptr, c.sc, c.part, tau_, 0, 0);
+    sch_.x_fwd_div(adj ? XM_RHS_ADJ : XM_RHS_FWD, c.T2, c.T3, c.X, c.R, nullptr, c.sc, c.part, tau_,
+                   0, 0, c.nb, st_);
     TG_LAUNCH_CHECK();
-    k_finalize<FIN_INIT><<<c.nb, 256, 0, st_>>>(c.sc, c.part, SX::NBLK, 1.0 / REAL, rtol(), d_.maxit);
+    k_finalize<FIN_INIT><<<c.nb, 256, 0, st_>>>(c.sc, c.part, sch_.sx_nblk, 1.0 / REAL, rtol(),
+                                                maxit());
     TG_LAUNCH_CHECK();
     return pcg_loop(c);
+  }
+
+  // In graph mode the iteration budget is the iteration cap, so a solve
+  // that needs more is flagged NOT_CONVERGED instead of silently stopping.
+  int maxit() const {
+    return graph_budget_ > 0 ? std::min(graph_budget_, d_.maxit) : d_.maxit;
   }
 
   double rtol() const {
@@ -291,20 +328,19 @@ class Solver final : public ISolver {
 
   void pcg_iteration(const Ctx& c) {
     timed(KT_X_INV_GRAD, 0, [&] {
-      k_x_inv_grad<T, N, C, 1><<<dim3(SX::NBLK, c.nb), SX::NT, 0, st_>>>(c.P, c.R, c.T1, c.T2,
-                                                                         c.sc, tau_, 1);
+      sch_.x_inv_grad(1, c.P, c.R, c.T1, c.T2, c.sc, tau_, 1, c.nb, st_);
     });
     matvec_mid(c, c.T1, c.T2, c.T3, 1);
     timed(KT_X_FWD_DIV, 0, [&] {
-      k_x_fwd_div<T, N, C, XM_PCG><<<dim3(SX::NBLK, c.nb), SX::NT, 0, st_>>>(
-          c.T1, c.T2, c.P, c.Q, nullptr, c.sc, c.part, tau_, 1, 0);
+      sch_.x_fwd_div(XM_PCG, c.T1, c.T2, c.P, c.Q, nullptr, c.sc, c.part, tau_, 1, 0, c.nb, st_);
     });
-    k_finalize<FIN_PQ><<<c.nb, 256, 0, st_>>>(c.sc, c.part, SX::NBLK, 1.0 / REAL, rtol(), d_.maxit);
+    k_finalize<FIN_PQ><<<c.nb, 256, 0, st_>>>(c.sc, c.part, sch_.sx_nblk, 1.0 / REAL, rtol(),
+                                              maxit());
     timed(KT_PCG_UPDATE, 0, [&] {
       k_pcg_update<T, N><<<dim3(W::NBLK, c.nb), 256, 0, st_>>>(c.X, c.R, c.P, c.Q, c.sc, c.part,
                                                                tau_);
     });
-    k_finalize<FIN_RZ><<<c.nb, 256, 0, st_>>>(c.sc, c.part, W::NBLK, 1.0 / REAL, rtol(), d_.maxit);
+    k_finalize<FIN_RZ><<<c.nb, 256, 0, st_>>>(c.sc, c.part, W::NBLK, 1.0 / REAL, rtol(), maxit());
   }
 
   // ------------------------------------------------------ kernel timer
@@ -377,6 +413,11 @@ class Solver final : public ISolver {
   // Launch predicated iterations in chunks; synchronize only to read the
   // done flags between chunks.
   hipError_t pcg_loop(const Ctx& c) {
+    if (graph_budget_ > 0) {
+      // graph capture: a fixed, predicated iteration budget, no host reads
+      for (int i = 0; i < graph_budget_; ++i) pcg_iteration(c);
+      return hipGetLastError();
+    }
     int launched = 0;
     int chunk = std::max(1, its_est_);
     int maxseen = 0;
@@ -398,6 +439,7 @@ class Solver final : public ISolver {
       chunk = std::max(2, its_est_ / 4);
     }
     its_est_ = std::max(1, maxseen);
+    its_max_call_ = std::max(its_max_call_, maxseen);
     if (tm_id_ != KT_NONE) {
       long long eff = 0;
       for (int b = 0; b < c.nb; ++b) eff += hsc_[b].its;
@@ -484,19 +526,18 @@ class Solver final : public ISolver {
         }
         TG_LAUNCH_CHECK();
         if (!gn) {
-          k_finalize<FIN_GRHO><<<c.nb, 256, 0, st_>>>(c.sc, c.part, Z::NBLK, 1.0, 0, 0);
+          k_finalize<FIN_GRHO><<<c.nb, 256, 0, st_>>>(c.sc, c.part, sch_.z_nblk, 1.0, 0, 0);
           TG_LAUNCH_CHECK();
         }
         TG_CHECK(step_solve(c, true));
         // lam_a = mu + tau k_f A_m mu; g_k += tau <A_m mu, a + b>
-        k_x_inv_grad<T, N, C, 0><<<dim3(SX::NBLK, c.nb), SX::NT, 0, st_>>>(c.X, nullptr, c.T1, c.T2,
-                                                                           c.sc, tau_, 0);
+        sch_.x_inv_grad(0, c.X, nullptr, c.T1, c.T2, c.sc, tau_, 0, c.nb, st_);
         matvec_mid(c, c.T1, c.T2, c.T3, 0);
-        k_x_fwd_div<T, N, C, XM_POST_ADJ><<<dim3(SX::NBLK, c.nb), SX::NT, 0, st_>>>(
-            c.T1, c.T2, c.X, nullptr, c.S, c.sc, c.part, tau_, 0, gn ? 0 : 1);
+        sch_.x_fwd_div(XM_POST_ADJ, c.T1, c.T2, c.X, nullptr, c.S, c.sc, c.part, tau_, 0,
+                       gn ? 0 : 1, c.nb, st_);
         TG_LAUNCH_CHECK();
         if (!gn) {
-          k_finalize<FIN_GK><<<c.nb, 256, 0, st_>>>(c.sc, c.part, SX::NBLK, tau_ / REAL, 0, 0);
+          k_finalize<FIN_GK><<<c.nb, 256, 0, st_>>>(c.sc, c.part, sch_.sx_nblk, tau_ / REAL, 0, 0);
           TG_LAUNCH_CHECK();
         }
       }
@@ -511,7 +552,7 @@ class Solver final : public ISolver {
     launch_z<ZS_ADJ_LAST>(a, c.nb);
     TG_LAUNCH_CHECK();
     if (!gn) {
-      k_finalize<FIN_GRHO><<<c.nb, 256, 0, st_>>>(c.sc, c.part, Z::NBLK, 1.0, 0, 0);
+      k_finalize<FIN_GRHO><<<c.nb, 256, 0, st_>>>(c.sc, c.part, sch_.z_nblk, 1.0, 0, 0);
       TG_LAUNCH_CHECK();
     }
     return hipSuccess;
@@ -544,6 +585,11 @@ class Solver final : public ISolver {
   int its_est_;
   int live_seg_ = -1;
   int call_status_ = 0;
+  int graph_budget_ = 0;
+  int its_max_call_ = 0;
+  Sched<T, N> sch_;
+  int zwaves_ = 0;
+  int nslab_ = 1;
   ProbScalars* stat_sc_ = nullptr;
   int stat_nb_ = 0;
   // kernel timer state
@@ -559,19 +605,6 @@ class Solver final : public ISolver {
     for (auto& e : tm_ev_) hipEventDestroy(e);
   }
 };
-
-template <typename T>
-ISolver* make_solver_t(const SolverDims& d, const Workspace& w) {
-  switch (d.n) {
-    case 8: return new Solver<T, 8>(d, w);
-    case 16: return new Solver<T, 16>(d, w);
-    case 32: return new Solver<T, 32>(d, w);
-    case 64: return new Solver<T, 64>(d, w);
-    case 128: return new Solver<T, 128>(d, w);
-    case 256: return new Solver<T, 256>(d, w);
-    default: return nullptr;
-  }
-}
 
 template <typename T>
 hipError_t fill_twiddles() {

@@ -239,3 +239,41 @@ def test_autograd_function_fp64():
     assert rel(pt.grad.cpu().numpy(), g.g_p) < 1e-10
     assert abs(rt.grad.item() - g.g_rho) < 1e-10 * abs(g.g_rho)
     assert abs(kt.grad.item() - g.g_k) < 1e-10 * abs(g.g_k)
+
+
+# ------------------------------------------------------- batch graph
+def test_batch_graph_replays_match_eager():
+    """Two plans of different grid sizes captured into one graph; every
+    replay (with eager work and synchronizations in between) reproduces the
+    eager gradients bit for bit."""
+    print("case batch_graph", flush=True)
+    items, eager = [], []
+    for n, nb, seed0 in ((16, 3, 1), (32, 2, 5)):
+        probs = [case(n, 2, seed0 + s, 4, 5.0 + s, 0.1 + 0.05 * s) for s in range(nb)]
+        prs = [q[0] for q in probs]
+        cen = np.stack([q.centres for q in prs])
+        plan = api.Plan(n, 4, cen, prs[0].sigma, rtol=1e-8, batch=nb, precision="fp32",
+                        ckpt_stride=2)
+        p = np.stack([q[1] for q in probs])
+        rho = [q.rho_f for q in prs]
+        kf = [q.k_f for q in prs]
+        m = np.stack([q.m for q in prs])
+        d = np.stack([inputs.random_field(n, 40 + s) for s in range(nb)])
+        plan.forward(p, rho, kf, m)
+        J, gp, gr, gk = plan.adjoint_misfit(d)
+        eager.append([t.detach().cpu().numpy().copy() for t in (J, gp, gr, gk)])
+        items.append((plan, p, rho, kf, m, d))
+    bg = api.BatchGraph(items)
+    for rep in range(3):
+        bg.launch()
+        torch.cuda.synchronize()
+        for (J, gp, gr, gk), ref in zip(bg.results(), eager):
+            got = [t.detach().cpu().numpy() for t in (J, gp, gr, gk)]
+            for a, b in zip(got, ref):
+                assert np.array_equal(a.ravel(), b.ravel()), f"replay {rep} differs"
+        # unrelated eager work between replays
+        x = torch.randn(1 << 20, device="cuda:0")
+        assert torch.isfinite(x.sum())
+        torch.cuda.synchronize()
+    for pl in bg.plans:
+        assert pl.stats().status_bits == 0
