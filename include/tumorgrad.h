@@ -73,7 +73,10 @@ typedef struct tg_desc {
                             copied at tg_plan_bind */
   double sigma;          /* Gaussian standard deviation, > 0 */
   double pcg_rtol;       /* PCG stop: ||r|| <= rtol ||rhs||, 0 < rtol < 1.
-                            TG_FP32_MIXED stops no lower than 50 eps_32. */
+                            TG_FP32_MIXED stops no lower than a floor,
+                            50 eps_32 = 6e-6 unless the environment variable
+                            TUMORGRAD_FP32_RTOL_FLOOR (read when the plan is
+                            bound) sets another value. */
   int pcg_maxit;         /* >= 1 */
   int ckpt_stride;       /* 0: keep every step's state; s > 0: keep every
                             s-th state and recompute segments in the adjoint */
@@ -136,11 +139,14 @@ tg_status tg_hessvec_gn(tg_plan* plan, int ndir, const double* d_V, double* d_HV
  * are identical up to the summation order of the FP64 partial sums).
  * pencils: 8, 16 or 32 pencils per x/y-pass workgroup; z_waves: 1, 2 or 4
  * waves per z-pass workgroup; slabs: 1, 2, 4 or 8 x-plane slabs over which
- * the y-z-y pass chain of the diffusion operator runs slab by slab; 0
- * selects the default.  Requires a bound plan.  Errors: TG_ERR_ARG for
- * unsupported values. */
-tg_status tg_plan_set_schedule(tg_plan* plan, int pencils, int z_waves, int slabs);
-tg_status tg_plan_get_schedule(const tg_plan* plan, int* pencils, int* z_waves, int* slabs);
+ * the y-z-y pass chain of the diffusion operator runs slab by slab;
+ * waves_per_simd: occupancy floor of the PCG pass kernels (1: registers
+ * uncapped, 4: capped so four waves fit per SIMD); 0 selects the default.
+ * Requires a bound plan.  Errors: TG_ERR_ARG for unsupported values. */
+tg_status tg_plan_set_schedule(tg_plan* plan, int pencils, int z_waves, int slabs,
+                               int waves_per_simd);
+tg_status tg_plan_get_schedule(const tg_plan* plan, int* pencils, int* z_waves, int* slabs,
+                               int* waves_per_simd);
 
 /* PCG statistics of the last call (synchronizes the plan's last stream). */
 tg_status tg_stats(tg_plan* plan, tg_solve_stats* out);

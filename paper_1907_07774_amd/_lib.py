@@ -91,9 +91,9 @@ def lib():
     L.tg_batch_launch.argtypes = [vp, vp]
     L.tg_batch_destroy.argtypes = [vp]
     L.tg_batch_destroy.restype = None
-    L.tg_plan_set_schedule.argtypes = [vp, C.c_int, C.c_int, C.c_int]
+    L.tg_plan_set_schedule.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int]
     L.tg_plan_get_schedule.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int),
-                                       C.POINTER(C.c_int)]
+                                       C.POINTER(C.c_int), C.POINTER(C.c_int)]
     for name in ("tg_plan_create", "tg_plan_workspace_bytes", "tg_plan_bind", "tg_forward",
                  "tg_vjp", "tg_adjoint_misfit", "tg_hessvec_gn", "tg_stats",
                  "tg_kernel_timer", "tg_kernel_timer_read", "tg_plan_set_schedule",

@@ -176,21 +176,23 @@ class Plan:
         return Stats(s.solves, s.pcg_its_total, s.pcg_its_max, s.status_bits,
                      s.worst_rel_residual)
 
-    def set_schedule(self, pencils: int = 0, z_waves: int = 0, slabs: int = 0):
+    def set_schedule(self, pencils: int = 0, z_waves: int = 0, slabs: int = 0,
+                     waves_per_simd: int = 0):
         """Choose the transform launch schedule (0 = default)."""
         if self._ws is None:
-            self._schedule = (int(pencils), int(z_waves), int(slabs))
+            self._schedule = (int(pencils), int(z_waves), int(slabs), int(waves_per_simd))
             self._bind()
             return
         _lib.check(_lib.lib().tg_plan_set_schedule(self._h, int(pencils), int(z_waves),
-                                                    int(slabs)), "tg_plan_set_schedule")
+                                                    int(slabs), int(waves_per_simd)),
+                   "tg_plan_set_schedule")
 
     def get_schedule(self):
         self._bind()
-        a, b, c = C.c_int(), C.c_int(), C.c_int()
-        _lib.check(_lib.lib().tg_plan_get_schedule(self._h, C.byref(a), C.byref(b), C.byref(c)),
+        v = [C.c_int() for _ in range(4)]
+        _lib.check(_lib.lib().tg_plan_get_schedule(self._h, *[C.byref(x) for x in v]),
                    "tg_plan_get_schedule")
-        return a.value, b.value, c.value
+        return tuple(x.value for x in v)
 
     KERNELS = {"x_inv_grad": 1, "y_inv_grad": 2, "z_matvec": 3, "y_fwd_div": 4,
                "x_fwd_div": 5, "pcg_update": 6}

@@ -17,6 +17,7 @@ DEFAULT_CACHE = os.path.join(PKG, "schedules.json")
 PENCILS = (8, 16, 32)
 Z_WAVES = (1, 2, 4)
 SLABS = (1, 2, 4, 8)
+OCCUPANCY = (1, 4)
 
 
 def cache_path() -> str:
@@ -41,7 +42,8 @@ def lookup(arch: str, n: int, precision: str, batch: int):
     ent = load().get(key(arch, n, precision, batch))
     if not ent:
         return None
-    return int(ent["pencils"]), int(ent["z_waves"]), int(ent.get("slabs", 1))
+    return (int(ent["pencils"]), int(ent["z_waves"]), int(ent.get("slabs", 1)),
+            int(ent.get("waves_per_simd", 1)))
 
 
 def gpu_arch(device) -> str:
@@ -51,10 +53,11 @@ def gpu_arch(device) -> str:
 
 
 def tune(plan, p, rho_f, k_f, m, reps: int = 2, candidates=None, verbose: bool = False):
-    """Time plan.forward for every (pencils, z_waves, slabs) candidate; set
-    and return the fastest with the table of timings (ms)."""
+    """Time plan.forward for every (pencils, z_waves, slabs, waves_per_simd)
+    candidate; set and return the fastest with the table of timings (ms)."""
     import torch
-    cands = candidates or [(c, w, s) for c in PENCILS for w in Z_WAVES for s in SLABS]
+    cands = candidates or [(c, w, s, o) for c in PENCILS for w in Z_WAVES for s in SLABS
+                           for o in OCCUPANCY]
     times = {}
     st = torch.cuda.current_stream(plan.device)
     for cand in cands:

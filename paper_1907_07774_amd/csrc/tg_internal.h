@@ -83,15 +83,16 @@ class ISolver {
   virtual hipError_t timer_enable(int id) = 0;
   virtual hipError_t timer_read(double* ms, long long* launches, double* work_bytes) = 0;
   // Transform tile shapes: pencils per x/y workgroup (8, 16, 32), waves
-  // per z workgroup (1, 2, 4) and x slabs of the y-z-y pass chain (1, 2,
-  // 4, 8); 0 = default.  False if not available.
-  virtual bool set_schedule(int C, int zwaves, int slabs) = 0;
+  // per z workgroup (1, 2, 4), x slabs of the y-z-y pass chain (1, 2, 4, 8)
+  // and an occupancy floor for the PCG pass kernels (1: none, 4: >= 4 waves
+  // per SIMD); 0 = default.  False if not available.
+  virtual bool set_schedule(int C, int zwaves, int slabs, int occ) = 0;
   // Graph-capture mode: every PCG solve runs exactly `budget` predicated
   // iterations with no host synchronization (0 = eager, adaptive).
   virtual void set_graph_budget(int budget) = 0;
   // Largest PCG iteration count of one solve seen since the last forward.
   virtual int its_max_last_call() const = 0;
-  virtual void get_schedule(int* C, int* zwaves, int* slabs) const = 0;
+  virtual void get_schedule(int* C, int* zwaves, int* slabs, int* occ) const = 0;
 };
 
 enum KernelId : int {

@@ -99,6 +99,11 @@ struct SP {
   }
 };
 
+// Launch bounds with an occupancy floor: at least W waves per SIMD (the
+// compiler then caps registers accordingly); W = 1 leaves them uncapped.
+#define TG_BOUNDS(NT, W) \
+  __attribute__((amdgpu_flat_work_group_size(1, NT), amdgpu_waves_per_eu(W)))
+
 #define SP_SETUP(AXV) SP_SETUP_OFF(AXV, 0)
 #define SP_SETUP_OFF(AXV, OFF)                                          \
   using S = SP<T, N, C, AXV>;                                           \
@@ -113,8 +118,8 @@ struct SP {
 // ---- x pass, inverse, gradient prologue of the diffusion matvec.
 // MODE 0: p is given.  MODE 1: PCG direction p = M r + beta p (stored).
 // Out: U1 = IFFT_x(s i wx p), U2 = IFFT_x(s p), s = 1/n^3.
-template <typename T, int N, int C, int MODE>
-__global__ void __launch_bounds__((SP<T, N, C, 0>::NT))
+template <typename T, int N, int C, int MODE, int OCC>
+__global__ void TG_BOUNDS((SP<T, N, C, 0>::NT), OCC)
 k_x_inv_grad(cx<T>* __restrict__ P, const cx<T>* __restrict__ Rr, cx<T>* __restrict__ U1,
              cx<T>* __restrict__ U2, const ProbScalars* __restrict__ sc, double tau, int pred) {
   SP_SETUP(0)
@@ -158,8 +163,8 @@ k_x_inv_grad(cx<T>* __restrict__ P, const cx<T>* __restrict__ Rr, cx<T>* __restr
 
 // ---- y pass, inverse: V1 = IFFT_y(U1) (in place), V2 = IFFT_y(i wy U2)
 // (in place), V3 = IFFT_y(U2).  Both inputs are loaded before any FFT.
-template <typename T, int N, int C>
-__global__ void __launch_bounds__((SP<T, N, C, 1>::NT))
+template <typename T, int N, int C, int OCC>
+__global__ void TG_BOUNDS((SP<T, N, C, 1>::NT), OCC)
 k_y_inv_grad(cx<T>* __restrict__ U1, cx<T>* __restrict__ U2, cx<T>* __restrict__ V3,
              const ProbScalars* __restrict__ sc, int pred, int blk0) {
   SP_SETUP_OFF(1, blk0)
@@ -185,8 +190,8 @@ k_y_inv_grad(cx<T>* __restrict__ U1, cx<T>* __restrict__ U2, cx<T>* __restrict__
 
 // ---- y pass, forward: W1 = FFT_y(H1) (in place), W23 = i wy FFT_y(H2) +
 // FFT_y(H3) (into H2).  FP32 loads all three inputs before any FFT.
-template <typename T, int N, int C>
-__global__ void __launch_bounds__((SP<T, N, C, 1>::NT))
+template <typename T, int N, int C, int OCC>
+__global__ void TG_BOUNDS((SP<T, N, C, 1>::NT), OCC)
 k_y_fwd_div(cx<T>* __restrict__ H1, cx<T>* __restrict__ H2, const cx<T>* __restrict__ H3,
             const ProbScalars* __restrict__ sc, int pred, int blk0) {
   SP_SETUP_OFF(1, blk0)
@@ -228,8 +233,8 @@ enum XMode : int {
   XM_POST_ADJ = 3  // X += tau kf Am; partial <Am, S> (k_f gradient)
 };
 
-template <typename T, int N, int C, int MODE>
-__global__ void __launch_bounds__((SP<T, N, C, 0>::NT))
+template <typename T, int N, int C, int MODE, int OCC>
+__global__ void TG_BOUNDS((SP<T, N, C, 0>::NT), OCC)
 k_x_fwd_div(const cx<T>* __restrict__ W1, const cx<T>* __restrict__ W23, cx<T>* __restrict__ X,
             cx<T>* __restrict__ Q, const cx<T>* __restrict__ Sv, const ProbScalars* __restrict__ sc,
             double* __restrict__ part, double tau, int pred, int want_gk) {
@@ -499,10 +504,10 @@ __device__ __forceinline__ void r2c_row(cx<T> (&v)[E], cx<T>* lds, int t, int ro
 // m, R2C, (z: times i wz).  In place on V1..V3.  The launch covers the
 // blocks [blk0, blk0 + gridDim.x) (a slab of x planes); rev walks them from
 // the last to the first (the y pass before it ends at the last rows, whose
-// output is then still in the last-level cache).  FP32 loads all three
-// rows up front.
-template <typename T, int N, int RW>
-__global__ void __launch_bounds__((ZP<T, N, RW>::NT))
+// output is then still in the last-level cache).  PRE = 3 loads all three
+// rows up front; PRE = 1 loads each before its use (fewer registers).
+template <typename T, int N, int RW, int PRE_, int OCC>
+__global__ void TG_BOUNDS((ZP<T, N, RW>::NT), OCC)
 k_z_matvec(cx<T>* __restrict__ V1, cx<T>* __restrict__ V2, cx<T>* __restrict__ V3,
            const T* __restrict__ m, long long m_bs, const ProbScalars* __restrict__ sc, int pred,
            int rev, int blk0) {
@@ -517,10 +522,14 @@ k_z_matvec(cx<T>* __restrict__ V1, cx<T>* __restrict__ V2, cx<T>* __restrict__ V
   const long long sbase = (long long)b * Z::SPEC + grow * Z::L;
   const cx<T>* mrow = reinterpret_cast<const cx<T>*>(m + b * m_bs + grow * N);
   cx<T>* Vs[3] = {V1 + sbase, V2 + sbase, V3 + sbase};
-  constexpr int PRE = sizeof(T) == 4 ? 3 : 1;  // rows held in registers at once
-  cx<T> mv[E], v[PRE][E];
+  constexpr int PRE = PRE_;  // rows held in registers at once (1 or 3)
+  // PRE = 3 keeps m in registers for all three rows; PRE = 1 re-reads the
+  // m row (a cache hit after the first row) to save registers.
+  cx<T> mv[PRE == 3 ? E : 1], v[PRE][E];
+  if constexpr (PRE == 3) {
 #pragma unroll
-  for (int e = 0; e < E; ++e) mv[e] = mrow[t + TT * e];
+    for (int e = 0; e < E; ++e) mv[e] = mrow[t + TT * e];
+  }
 #pragma unroll
   for (int j = 0; j < PRE; ++j)
 #pragma unroll
@@ -538,7 +547,10 @@ k_z_matvec(cx<T>* __restrict__ V1, cx<T>* __restrict__ V2, cx<T>* __restrict__ V
     }
     c2r_row<T, N>(u, lds, t, row);
 #pragma unroll
-    for (int e = 0; e < E; ++e) u[e] = mk(u[e].x * mv[e].x, u[e].y * mv[e].y);
+    for (int e = 0; e < E; ++e) {
+      const cx<T> me = PRE == 3 ? mv[PRE == 3 ? e : 0] : mrow[t + TT * e];
+      u[e] = mk(u[e].x * me.x, u[e].y * me.y);
+    }
     r2c_row<T, N>(u, lds, t, row);
 #pragma unroll
     for (int e = 0; e < E; ++e) {

@@ -33,26 +33,26 @@ struct Sched {
   void (*z_step)(int mode, const ZArgs& a, int nb, hipStream_t st) = nullptr;
 };
 
-template <typename T, int N, int C>
+template <typename T, int N, int C, int OCC>
 struct SLaunch {
   using SX = SP<T, N, C, 0>;
   using SY = SP<T, N, C, 1>;
   static void x_inv_grad(int mode, cx<T>* P, const cx<T>* R, cx<T>* U1, cx<T>* U2,
                          const ProbScalars* sc, double tau, int pred, int nb, hipStream_t st) {
     if (mode == 1)
-      k_x_inv_grad<T, N, C, 1><<<dim3(SX::NBLK, nb), SX::NT, 0, st>>>(P, R, U1, U2, sc, tau, pred);
+      k_x_inv_grad<T, N, C, 1, OCC><<<dim3(SX::NBLK, nb), SX::NT, 0, st>>>(P, R, U1, U2, sc, tau, pred);
     else
-      k_x_inv_grad<T, N, C, 0><<<dim3(SX::NBLK, nb), SX::NT, 0, st>>>(P, R, U1, U2, sc, tau, pred);
+      k_x_inv_grad<T, N, C, 0, OCC><<<dim3(SX::NBLK, nb), SX::NT, 0, st>>>(P, R, U1, U2, sc, tau, pred);
   }
   static void y_inv_grad(cx<T>* U1, cx<T>* U2, cx<T>* V3, const ProbScalars* sc, int pred, int nb,
                          int k, int nslab, hipStream_t st) {
     const int nbk = SY::NBLK / nslab;
-    k_y_inv_grad<T, N, C><<<dim3(nbk, nb), SY::NT, 0, st>>>(U1, U2, V3, sc, pred, k * nbk);
+    k_y_inv_grad<T, N, C, OCC><<<dim3(nbk, nb), SY::NT, 0, st>>>(U1, U2, V3, sc, pred, k * nbk);
   }
   static void y_fwd_div(cx<T>* H1, cx<T>* H2, const cx<T>* H3, const ProbScalars* sc, int pred,
                         int nb, int k, int nslab, hipStream_t st) {
     const int nbk = SY::NBLK / nslab;
-    k_y_fwd_div<T, N, C><<<dim3(nbk, nb), SY::NT, 0, st>>>(H1, H2, H3, sc, pred, k * nbk);
+    k_y_fwd_div<T, N, C, OCC><<<dim3(nbk, nb), SY::NT, 0, st>>>(H1, H2, H3, sc, pred, k * nbk);
   }
   static void x_fwd_div(int mode, const cx<T>* W1, const cx<T>* W23, cx<T>* X, cx<T>* Q,
                         const cx<T>* Sv, const ProbScalars* sc, double* part, double tau, int pred,
@@ -60,16 +60,16 @@ struct SLaunch {
     const dim3 g(SX::NBLK, nb);
     switch (mode) {
       case XM_PCG:
-        k_x_fwd_div<T, N, C, XM_PCG><<<g, SX::NT, 0, st>>>(W1, W23, X, Q, Sv, sc, part, tau, pred, want_gk);
+        k_x_fwd_div<T, N, C, XM_PCG, OCC><<<g, SX::NT, 0, st>>>(W1, W23, X, Q, Sv, sc, part, tau, pred, want_gk);
         break;
       case XM_RHS_FWD:
-        k_x_fwd_div<T, N, C, XM_RHS_FWD><<<g, SX::NT, 0, st>>>(W1, W23, X, Q, Sv, sc, part, tau, pred, want_gk);
+        k_x_fwd_div<T, N, C, XM_RHS_FWD, OCC><<<g, SX::NT, 0, st>>>(W1, W23, X, Q, Sv, sc, part, tau, pred, want_gk);
         break;
       case XM_RHS_ADJ:
-        k_x_fwd_div<T, N, C, XM_RHS_ADJ><<<g, SX::NT, 0, st>>>(W1, W23, X, Q, Sv, sc, part, tau, pred, want_gk);
+        k_x_fwd_div<T, N, C, XM_RHS_ADJ, OCC><<<g, SX::NT, 0, st>>>(W1, W23, X, Q, Sv, sc, part, tau, pred, want_gk);
         break;
       default:
-        k_x_fwd_div<T, N, C, XM_POST_ADJ><<<g, SX::NT, 0, st>>>(W1, W23, X, Q, Sv, sc, part, tau, pred, want_gk);
+        k_x_fwd_div<T, N, C, XM_POST_ADJ, OCC><<<g, SX::NT, 0, st>>>(W1, W23, X, Q, Sv, sc, part, tau, pred, want_gk);
         break;
     }
   }
@@ -100,15 +100,18 @@ struct SLaunch {
   }
 };
 
-template <typename T, int N, int RW>
+template <typename T, int N, int RW, int OCC>
 struct ZLaunch {
   using Z = ZP<T, N, RW>;
   static void z_matvec(cx<T>* V1, cx<T>* V2, cx<T>* V3, const T* m, long long m_bs,
                        const ProbScalars* sc, int pred, int rev, int nb, int k, int nslab,
                        hipStream_t st) {
     const int nbk = Z::NBLK / nslab;
-    k_z_matvec<T, N, RW><<<dim3(nbk, nb), Z::NT, 0, st>>>(V1, V2, V3, m, m_bs, sc, pred, rev,
-                                                           k * nbk);
+    // FP32 holds all three rows unless an occupancy floor asks for fewer
+    // registers; FP64 always streams them one at a time.
+    constexpr int PRE = (sizeof(T) == 4 && OCC < 4) ? 3 : 1;
+    k_z_matvec<T, N, RW, PRE, OCC><<<dim3(nbk, nb), Z::NT, 0, st>>>(V1, V2, V3, m, m_bs, sc, pred,
+                                                                     rev, k * nbk);
   }
   template <int MODE>
   static void zs(const ZArgs& a, int nb, hipStream_t st) {
@@ -137,29 +140,44 @@ struct ZLaunch {
 
 // Candidate tile shapes.  Pencils per x/y workgroup: 8, 16, 32 (row
 // segments of 64..512 bytes).  Rows per z workgroup: one, two or four waves.
-template <typename T, int N>
-bool set_strided(Sched<T, N>& s, int C) {
+template <typename T, int N, int OCC>
+bool set_strided_occ(Sched<T, N>& s, int C) {
   switch (C) {
-    case 8: SLaunch<T, N, 8>::fill(s); return true;
-    case 16: SLaunch<T, N, 16>::fill(s); return true;
-    case 32: SLaunch<T, N, 32>::fill(s); return true;
+    case 8: SLaunch<T, N, 8, OCC>::fill(s); return true;
+    case 16: SLaunch<T, N, 16, OCC>::fill(s); return true;
+    case 32: SLaunch<T, N, 32, OCC>::fill(s); return true;
+  }
+  return false;
+}
+
+// occ: occupancy floor in waves per SIMD (1: none, 4: at least four)
+template <typename T, int N>
+bool set_strided(Sched<T, N>& s, int C, int occ) {
+  if (occ == 4) return set_strided_occ<T, N, 4>(s, C);
+  if (occ == 1) return set_strided_occ<T, N, 1>(s, C);
+  return false;
+}
+
+template <typename T, int N, int OCC>
+bool set_zrows_occ(Sched<T, N>& s, int waves) {
+  constexpr int TT = ZP<T, N>::TT;
+  constexpr int r1 = 64 / TT;
+  switch (waves) {
+    case 1: ZLaunch<T, N, r1, OCC>::fill(s); return true;
+    case 2:
+      if constexpr (N * N >= 2 * r1) { ZLaunch<T, N, 2 * r1, OCC>::fill(s); return true; }
+      return false;
+    case 4:
+      if constexpr (N * N >= 4 * r1) { ZLaunch<T, N, 4 * r1, OCC>::fill(s); return true; }
+      return false;
   }
   return false;
 }
 
 template <typename T, int N>
-bool set_zrows(Sched<T, N>& s, int waves) {
-  constexpr int TT = ZP<T, N>::TT;
-  constexpr int r1 = 64 / TT;
-  switch (waves) {
-    case 1: ZLaunch<T, N, r1>::fill(s); return true;
-    case 2:
-      if constexpr (N * N >= 2 * r1) { ZLaunch<T, N, 2 * r1>::fill(s); return true; }
-      return false;
-    case 4:
-      if constexpr (N * N >= 4 * r1) { ZLaunch<T, N, 4 * r1>::fill(s); return true; }
-      return false;
-  }
+bool set_zrows(Sched<T, N>& s, int waves, int occ) {
+  if (occ == 4) return set_zrows_occ<T, N, 4>(s, waves);
+  if (occ == 1) return set_zrows_occ<T, N, 1>(s, waves);
   return false;
 }
 

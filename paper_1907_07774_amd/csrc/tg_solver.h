@@ -13,6 +13,7 @@
 #pragma once
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <vector>
 
 #include "tg_launch.h"
@@ -52,31 +53,39 @@ class Solver final : public ISolver {
     h3_ = h * h * h;
     hsc_.resize(d.batch + d.dirs);
     its_est_ = 8;
-    set_schedule(0, 0, 0);
+    set_schedule(0, 0, 0, 0);
+    fp32_floor_ = 50.0 * 1.1920928955078125e-07;
+    if (const char* f = std::getenv("TUMORGRAD_FP32_RTOL_FLOOR")) {
+      const double v = std::atof(f);
+      if (v > 0.0 && v < 1.0) fp32_floor_ = v;
+    }
   }
 
   // Tile shapes of the transform passes; 0 picks the default.
-  bool set_schedule(int C, int zwaves, int slabs) override {
+  bool set_schedule(int C, int zwaves, int slabs, int occ) override {
     Sched<T, N> s;
     if (C == 0) C = 16;
     if (zwaves == 0) zwaves = 1;
     if (slabs == 0) slabs = 1;
+    if (occ == 0) occ = 1;
     if (slabs != 1 && slabs != 2 && slabs != 4 && slabs != 8) return false;
-    if (!set_strided<T, N>(s, C)) return false;
-    if (!set_zrows<T, N>(s, zwaves)) {
-      if (!set_zrows<T, N>(s, 1)) return false;
+    if (!set_strided<T, N>(s, C, occ)) return false;
+    if (!set_zrows<T, N>(s, zwaves, occ)) {
+      if (!set_zrows<T, N>(s, 1, occ)) return false;
       zwaves = 1;
     }
     if (s.sy_nblk % slabs != 0 || s.z_nblk % slabs != 0) return false;
     sch_ = s;
     zwaves_ = zwaves;
     nslab_ = slabs;
+    occ_ = occ;
     return true;
   }
-  void get_schedule(int* C, int* zwaves, int* slabs) const override {
+  void get_schedule(int* C, int* zwaves, int* slabs, int* occ) const override {
     *C = sch_.C;
     *zwaves = zwaves_;
     *slabs = nslab_;
+    *occ = occ_;
   }
 
   // ------------------------------------------------------------ forward
@@ -320,9 +329,9 @@ class Solver final : public ISolver {
   }
 
   double rtol() const {
-    // FP32 arithmetic cannot certify residuals below a few hundred ulps:
-    // stop at the stagnation floor 50 eps_32 if rtol asks for less.
-    if (sizeof(T) == 4) return std::max(d_.rtol, 50.0 * 1.1920928955078125e-07);
+    // FP32 arithmetic cannot certify residuals near its rounding level:
+    // stop at a floor (default 50 eps_32) if rtol asks for less.
+    if (sizeof(T) == 4) return std::max(d_.rtol, fp32_floor_);
     return d_.rtol;
   }
 
@@ -586,10 +595,12 @@ class Solver final : public ISolver {
   int live_seg_ = -1;
   int call_status_ = 0;
   int graph_budget_ = 0;
+  double fp32_floor_ = 0.0;
   int its_max_call_ = 0;
   Sched<T, N> sch_;
   int zwaves_ = 0;
   int nslab_ = 1;
+  int occ_ = 1;
   ProbScalars* stat_sc_ = nullptr;
   int stat_nb_ = 0;
   // kernel timer state

@@ -18,7 +18,7 @@ def tune_case(n, precision, batch, nt, seed, verbose=True, candidates=None):
     probs = [inputs.problem(n, 2 if n <= 64 else 4, seed + b, nt=nt) for b in range(batch)]
     cen = np.stack([q.centres for q in probs])
     plan = api.Plan(n, nt, cen, probs[0].sigma, rtol=1e-8, precision=precision, batch=batch,
-                    schedule=(0, 0, 0))
+                    schedule=(0, 0, 0, 0))
     dt = plan.dtype
     dev = plan.device
     m = torch.tensor(np.stack([q.m for q in probs]), dtype=dt, device=dev)
@@ -30,7 +30,8 @@ def tune_case(n, precision, batch, nt, seed, verbose=True, candidates=None):
     best, times = autotune.tune(plan, p, rho, kf, m, verbose=verbose, candidates=candidates)
     arch = autotune.gpu_arch(dev)
     k = autotune.key(arch, n, precision, batch)
-    ent = {"pencils": best[0], "z_waves": best[1], "slabs": best[2], "ms": times[best],
+    ent = {"pencils": best[0], "z_waves": best[1], "slabs": best[2],
+           "waves_per_simd": best[3] if len(best) > 3 else 1, "ms": times[best],
            "table_ms": {"x".join(map(str, k)): round(t, 4) for k, t in times.items()}}
     del plan
     torch.cuda.empty_cache()
@@ -46,7 +47,8 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", default=None)
     ap.add_argument("--candidates", default=None,
-                    help="comma-separated pencils x z_waves x slabs, e.g. 16x1x1,32x1x2")
+                    help="comma-separated pencils x z_waves x slabs x waves_per_simd, "
+                         "e.g. 16x1x1x1,32x1x1x4")
     a = ap.parse_args(argv)
     cands = None
     if a.candidates:

@@ -1,0 +1,76 @@
+"""Write oracle reference values for the GPU parity tests at the
+benchmark configurations (calls only the FP64 oracle and the input
+generators).
+
+    python tests/golden/make_golden.py config2      # 128^3 gradient
+    python tests/golden/make_golden.py config3fwd   # 256^3 forward, sampled
+
+Outputs are small .npz files next to this script: scalars, the full
+gradient vector and c(T) at a seeded sample of grid points.
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle import tumor  # noqa: E402
+from paper_1907_07774_amd import inputs  # noqa: E402
+
+NSAMPLE = 4096
+
+
+def sample_idx(n, seed=123):
+    rng = np.random.default_rng(seed)
+    return rng.choice(n ** 3, NSAMPLE, replace=False)
+
+
+def config2(rtol=1e-13):
+    """128^3, 64 Gaussians, rho_f = 10, k_f = 0.1, T = 1, nt = 16; synthetic
+    observation: threshold of a perturbed-p run."""
+    n, nt, seed = 128, 16, 2
+    pr = inputs.problem(n, 4, seed, nt=nt, rho_f=10.0, k_f=0.1)
+    su = tumor.Setup(pr.m, pr.centres, pr.sigma, pr.rho_f, pr.k_f, nt, rtol=rtol)
+    t0 = time.time()
+    d = inputs.threshold_mask(tumor.forward(su, inputs.perturbed_p(pr.p, seed)).c[-1])
+    J, g, tr = tumor.gradient(su, pr.p, d)
+    idx = sample_idx(n)
+    np.savez_compressed(os.path.join(HERE, "config2_128.npz"), n=n, nt=nt, seed=seed,
+                        rho_f=pr.rho_f, k_f=pr.k_f, rtol=rtol, J=J, g_p=g.g_p, g_rho=g.g_rho,
+                        g_k=g.g_k, idx=idx, cT=tr.c[-1].ravel()[idx],
+                        cT_norm=np.linalg.norm(tr.c[-1]), d_idx=np.flatnonzero(d.ravel()),
+                        its_fwd=np.array(tr.its), its_adj=np.array(g.its))
+    print(f"config2 done in {time.time() - t0:.0f} s: J={J:.6e}", flush=True)
+
+
+def config3fwd(rtol=1e-10):
+    """256^3 forward of the benchmark problem (seed 0, 64 Gaussians, rho_f and
+    k_f drawn from the seed, nt = 32): c(T) at sampled points."""
+    n, nt, seed = 256, 32, 0
+    pr = inputs.problem(n, 4, seed, nt=nt)
+    su = tumor.Setup(pr.m, pr.centres, pr.sigma, pr.rho_f, pr.k_f, nt, rtol=rtol)
+    t0 = time.time()
+    c = tumor.phi(pr.p, pr.centres, pr.sigma, n)
+    tau = 0.5 * su.dt
+    its = []
+    for _ in range(nt):  # the oracle's forward step, keeping only the state
+        a = tumor.reaction(c, su.m, su.rho_f, tau)
+        rhs = a + tau * su.k_f * tumor._A_m(su, a)
+        b, it = tumor._cn_solve(su, rhs, a)
+        c = tumor.reaction(b, su.m, su.rho_f, tau)
+        its.append(it)
+        print(f"  step {len(its)}/{nt}: {it} its, {time.time() - t0:.0f} s", flush=True)
+    idx = sample_idx(n)
+    np.savez_compressed(os.path.join(HERE, "config3_256_forward.npz"), n=n, nt=nt, seed=seed,
+                        rho_f=pr.rho_f, k_f=pr.k_f, rtol=rtol, idx=idx, cT=c.ravel()[idx],
+                        cT_norm=np.linalg.norm(c), cT_sum=c.sum(), its=np.array(its))
+    print(f"config3fwd done in {time.time() - t0:.0f} s", flush=True)
+
+
+if __name__ == "__main__":
+    which = sys.argv[1:] or ["config2"]
+    for w in which:
+        globals()[w]()

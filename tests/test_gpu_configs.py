@@ -1,0 +1,224 @@
+"""GPU parity at the benchmark configurations' sizes.
+
+64^3 (forward, 8 Gaussians): element by element against the live oracle.
+128^3 (gradient, 64 Gaussians): against oracle values stored by
+tests/golden/make_golden.py, plus central finite differences of the FP64
+GPU path.  256^3 (the benchmark workload): sampled outputs the oracle can
+compute point by point (reaction-only closed form), stored sampled oracle
+forward values when present, and properties that hold at any size
+(checkpoint recompute bitwise, FP32-mixed vs FP64, Hessian symmetry).
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import tumor
+from paper_1907_07774_amd import api, inputs
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+# -------------------------------------------------------------- 64^3
+@pytest.mark.parametrize("rtol,tol", [(1e-13, 1e-10), (1e-8, 1e-7)])
+def test_config1_forward_64(rtol, tol):
+    """64^3, 8 Gaussians with p ~ U[0,1], rho_f = 10, k_f = 0.1, T = 1,
+    nt = 16.  At rtol 1e-8 two PCG implementations agree to ~kappa 1e-8."""
+    print(f"case config1 rtol={rtol}", flush=True)
+    pr = inputs.problem(64, 2, 1, nt=16, rho_f=10.0, k_f=0.1)
+    su = tumor.Setup(pr.m, pr.centres, pr.sigma, pr.rho_f, pr.k_f, 16, rtol=rtol)
+    tr = tumor.forward(su, pr.p)
+    for prec, t in (("fp64", tol), ("fp32", 1e-4)):
+        plan = api.Plan(64, 16, pr.centres, pr.sigma, rtol=rtol, precision=prec)
+        cT = plan.forward(pr.p, pr.rho_f, pr.k_f, pr.m).cpu().numpy()
+        assert rel(cT, tr.c[-1]) < t, prec
+
+
+# ------------------------------------------------------------- 128^3
+def load_golden(name):
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        pytest.skip(f"{name} not generated (tests/golden/make_golden.py)")
+    return np.load(path)
+
+
+def config2_problem(g):
+    pr = inputs.problem(int(g["n"]), 4, int(g["seed"]), nt=int(g["nt"]),
+                        rho_f=float(g["rho_f"]), k_f=float(g["k_f"]))
+    d = np.zeros(pr.n ** 3)
+    d[g["d_idx"]] = 1.0
+    return pr, d.reshape(pr.m.shape)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
+def test_config2_gradient_128(prec, tol):
+    print(f"case config2 {prec}", flush=True)
+    g = load_golden("config2_128.npz")
+    pr, d = config2_problem(g)
+    plan = api.Plan(pr.n, pr.nt, pr.centres, pr.sigma, rtol=float(g["rtol"]), precision=prec,
+                    ckpt_stride=4)
+    cT = plan.forward(pr.p, pr.rho_f, pr.k_f, pr.m).cpu().numpy().ravel()
+    J, gp, gr, gk = plan.adjoint_misfit(d)
+    assert np.linalg.norm(cT[g["idx"]] - g["cT"]) / np.linalg.norm(g["cT"]) < tol
+    assert abs(float(J) - float(g["J"])) < tol * abs(float(g["J"]))
+    assert rel(gp.cpu().numpy(), g["g_p"]) < tol
+    assert abs(float(gr) - float(g["g_rho"])) < tol * abs(float(g["g_rho"]))
+    assert abs(float(gk) - float(g["g_k"])) < tol * abs(float(g["g_k"]))
+
+
+def test_config2_central_fd_128():
+    """Central differences (step 1e-6 max(1, |theta|)) of the FP64 GPU
+    objective against the FP64 GPU adjoint gradient, rtol 1e-13."""
+    print("case config2 fd", flush=True)
+    pr = inputs.problem(128, 4, 2, nt=16, rho_f=10.0, k_f=0.1)
+    plan = api.Plan(128, 16, pr.centres, pr.sigma, rtol=1e-13, precision="fp64")
+    d = (plan.forward(inputs.perturbed_p(pr.p, 2), pr.rho_f, pr.k_f, pr.m) > 0.5).double()
+    plan.forward(pr.p, pr.rho_f, pr.k_f, pr.m)
+    _, gp, gr, gk = plan.adjoint_misfit(d)
+    gp = gp.cpu().numpy()
+
+    def J(p, rho, kf):
+        plan.forward(p, rho, kf, pr.m)
+        return float(plan.adjoint_misfit(d)[0])
+
+    h = 1e-6 * max(1.0, pr.rho_f)
+    fd = (J(pr.p, pr.rho_f + h, pr.k_f) - J(pr.p, pr.rho_f - h, pr.k_f)) / (2 * h)
+    assert abs(fd - float(gr)) < 1e-6 * abs(float(gr))
+    h = 1e-6
+    fd = (J(pr.p, pr.rho_f, pr.k_f + h) - J(pr.p, pr.rho_f, pr.k_f - h)) / (2 * h)
+    assert abs(fd - float(gk)) < 1e-6 * abs(float(gk))
+    for s in range(2):
+        u = inputs.hvp_directions(1, pr.p.size, 50 + s)[0]
+        fd = (J(pr.p + h * u, pr.rho_f, pr.k_f) - J(pr.p - h * u, pr.rho_f, pr.k_f)) / (2 * h)
+        assert abs(fd - gp @ u) < 1e-6 * np.linalg.norm(gp)
+
+
+# ------------------------------------------------------------- 256^3
+@pytest.fixture(scope="module")
+def bench_problem():
+    return inputs.problem(256, 4, 0, nt=32)
+
+
+def test_config3_reaction_only_closed_form_256(bench_problem):
+    """k_f = 0 at the benchmark size: c(T) = R_T(Phi p) point by point.
+    The path still takes 32 transform round trips.  Their rounding error is
+    absolute (relative to max c) and grows like exp(rho_f m t) where c is
+    tiny, the linearized logistic growth: about 1e-11 in FP64 and 1e-3 in
+    FP32 at such points, so FP32 is held to the relative L2 bound."""
+    print("case config3 reaction-only", flush=True)
+    pr = bench_problem
+    idx = np.random.default_rng(7).choice(256 ** 3, 2000, replace=False)
+    c0 = tumor.phi(pr.p, pr.centres, pr.sigma, 256).ravel()[idx]
+    mm = pr.m.ravel()[idx]
+    expect = tumor.reaction(c0, mm, pr.rho_f, 1.0)
+    for prec in ("fp64", "fp32"):
+        plan = api.Plan(256, 32, pr.centres, pr.sigma, rtol=1e-8, precision=prec, ckpt_stride=4)
+        cT = plan.forward(pr.p, pr.rho_f, 0.0, pr.m).cpu().numpy().ravel()[idx]
+        if prec == "fp64":
+            assert np.abs(cT - expect).max() < 1e-10 * max(1.0, np.abs(expect).max())
+        else:
+            assert rel(cT, expect) < 1e-4
+        del plan
+        torch.cuda.empty_cache()
+
+
+def test_config3_forward_vs_oracle_samples_256(bench_problem):
+    print("case config3 forward samples", flush=True)
+    g = load_golden("config3_256_forward.npz")
+    pr = bench_problem
+    for prec, tol in (("fp64", 1e-8), ("fp32", 1e-4)):
+        plan = api.Plan(256, 32, pr.centres, pr.sigma, rtol=float(g["rtol"]), precision=prec,
+                        ckpt_stride=4)
+        cT = plan.forward(pr.p, pr.rho_f, pr.k_f, pr.m).cpu().numpy().ravel()
+        assert np.linalg.norm(cT[g["idx"]] - g["cT"]) / np.linalg.norm(g["cT"]) < tol, prec
+        del plan
+        torch.cuda.empty_cache()
+
+
+@pytest.fixture(scope="module")
+def grads_256(bench_problem):
+    """FP64 and FP32-mixed gradients of the benchmark workload, plus the
+    FP32-mixed gradient without checkpointing."""
+    pr = bench_problem
+    obs = api.Plan(256, 32, pr.centres, pr.sigma, rtol=1e-8, precision="fp32", ckpt_stride=4)
+    d = (obs.forward(inputs.perturbed_p(pr.p, 0), pr.rho_f, pr.k_f, pr.m) > 0.5).double()
+    del obs
+    out = {}
+    for key, prec, ck in (("fp64", "fp64", 4), ("fp32", "fp32", 4), ("fp32_nockpt", "fp32", 0)):
+        plan = api.Plan(256, 32, pr.centres, pr.sigma, rtol=1e-8, precision=prec, ckpt_stride=ck)
+        plan.forward(pr.p, pr.rho_f, pr.k_f, pr.m)
+        J, gp, gr, gk = plan.adjoint_misfit(d)
+        out[key] = (float(J), gp.cpu().numpy(), float(gr), float(gk))
+        assert plan.stats().status_bits == 0
+        del plan
+        torch.cuda.empty_cache()
+    return out
+
+
+def test_config3_checkpoint_recompute_bitwise_256(grads_256):
+    print("case config3 ckpt bitwise", flush=True)
+    a, b = grads_256["fp32"], grads_256["fp32_nockpt"]
+    assert a[0] == b[0] and a[2] == b[2] and a[3] == b[3]
+    assert np.array_equal(a[1], b[1])
+
+
+def test_config3_fp32_mixed_vs_fp64_256(grads_256):
+    print("case config3 fp32 vs fp64", flush=True)
+    a, b = grads_256["fp32"], grads_256["fp64"]
+    assert abs(a[0] - b[0]) < 1e-4 * abs(b[0])
+    assert rel(a[1], b[1]) < 1e-4
+    assert abs(a[2] - b[2]) < 1e-4 * abs(b[2])
+    assert abs(a[3] - b[3]) < 1e-4 * abs(b[3])
+
+
+def test_config5_hessvec_256(bench_problem):
+    """8 Gauss-Newton directions at 256^3 (FP32-mixed): symmetry of V^T H V,
+    positivity, and agreement with the FP64 product on two directions."""
+    print("case config5 hessvec", flush=True)
+    pr = bench_problem
+    V = inputs.hvp_directions(8, pr.p.size, 0)
+    res = {}
+    for prec, nd in (("fp32", 8), ("fp64", 2)):
+        plan = api.Plan(256, 32, pr.centres, pr.sigma, rtol=1e-8, precision=prec, ckpt_stride=4,
+                        max_hvp_dirs=nd)
+        plan.forward(pr.p, pr.rho_f, pr.k_f, pr.m)
+        res[prec] = plan.hessvec(V[:nd]).cpu().numpy()
+        assert plan.stats().status_bits == 0
+        del plan
+        torch.cuda.empty_cache()
+    H = V @ res["fp32"].T
+    assert np.abs(H - H.T).max() < 1e-4 * np.abs(H).max()
+    assert np.all(np.diag(H) > 0)
+    for i in range(2):
+        assert rel(res["fp32"][i], res["fp64"][i]) < 1e-4
+
+
+# ---------------------------------------------------------- batched
+def test_config4_batch_equals_single_64():
+    """Problems solved in one batched plan give the same bits as the same
+    problems solved one plan each (kernels and reduction order are per
+    problem)."""
+    print("case config4 batch vs single", flush=True)
+    probs = [inputs.problem(64, 2, s, nt=16) for s in range(3)]
+    cen = np.stack([q.centres for q in probs])
+    d = np.stack([inputs.random_field(64, 60 + s) for s in range(3)]).astype(np.float32)
+    bp = api.Plan(64, 16, cen, probs[0].sigma, rtol=1e-8, precision="fp32", batch=3,
+                  ckpt_stride=4)
+    bp.forward(np.stack([q.p for q in probs]), [q.rho_f for q in probs],
+               [q.k_f for q in probs], np.stack([q.m for q in probs]))
+    J, gp, gr, gk = bp.adjoint_misfit(d)
+    for s, q in enumerate(probs):
+        sp = api.Plan(64, 16, q.centres, q.sigma, rtol=1e-8, precision="fp32", ckpt_stride=4)
+        sp.forward(q.p, q.rho_f, q.k_f, q.m)
+        J1, gp1, gr1, gk1 = sp.adjoint_misfit(d[s])
+        assert float(J[s]) == float(J1)
+        assert np.array_equal(gp[s].cpu().numpy(), gp1.cpu().numpy())
+        assert float(gr[s]) == float(gr1) and float(gk[s]) == float(gk1)
