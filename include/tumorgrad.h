@@ -138,7 +138,8 @@ tg_status tg_hessvec_gn(tg_plan* plan, int ndir, const double* d_V, double* d_HV
 /* Launch schedule of the transform passes (performance knobs only; results
  * are identical up to the summation order of the FP64 partial sums).
  * pencils: 8, 16 or 32 pencils per x/y-pass workgroup; z_waves: 1, 2 or 4
- * waves per z-pass workgroup; slabs: 1, 2, 4 or 8 x-plane slabs over which
+ * waves per z-pass workgroup, or 8 for one-wave workgroups whose matvec
+ * z pass spreads each row over twice the default lanes; slabs: 1, 2, 4 or 8 x-plane slabs over which
  * the y-z-y pass chain of the diffusion operator runs slab by slab;
  * waves_per_simd: occupancy floor of the PCG pass kernels (1: registers
  * uncapped, 4: capped so four waves fit per SIMD); 0 selects the default.

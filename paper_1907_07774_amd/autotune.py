@@ -15,7 +15,7 @@ import time
 PKG = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(PKG, "schedules.json")
 PENCILS = (8, 16, 32)
-Z_WAVES = (1, 2, 4)
+Z_WAVES = (1, 2, 4, 8)
 SLABS = (1, 2, 4, 8)
 OCCUPANCY = (1, 4)
 

@@ -255,7 +255,8 @@ tg_status tg_plan_set_schedule(tg_plan* plan, int pencils, int z_waves, int slab
   if (plan == nullptr) return TG_ERR_ARG;
   if (!plan->solver) return TG_ERR_WORKSPACE;
   if (!(pencils == 0 || pencils == 8 || pencils == 16 || pencils == 32)) return TG_ERR_ARG;
-  if (!(z_waves == 0 || z_waves == 1 || z_waves == 2 || z_waves == 4)) return TG_ERR_ARG;
+  if (!(z_waves == 0 || z_waves == 1 || z_waves == 2 || z_waves == 4 || z_waves == 8))
+    return TG_ERR_ARG;
   if (!(slabs == 0 || slabs == 1 || slabs == 2 || slabs == 4 || slabs == 8)) return TG_ERR_ARG;
   if (!(waves_per_simd == 0 || waves_per_simd == 1 || waves_per_simd == 4)) return TG_ERR_ARG;
   if (!plan->solver->set_schedule(pencils, z_waves, slabs, waves_per_simd)) return TG_ERR_ARG;

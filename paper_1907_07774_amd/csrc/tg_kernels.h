@@ -395,10 +395,10 @@ struct ZDefaultRows {
   static constexpr int value = (TT * 64 <= 256) ? 64 : 256 / TT;
 };
 
-template <typename T, int N, int RW_ = ZDefaultRows<N>::value>
+template <typename T, int N, int RW_ = ZDefaultRows<N>::value, int E_ = FftE<N / 2>::value>
 struct ZP {
   static constexpr int L = N / 2;
-  static constexpr int E = FftE<L>::value;
+  static constexpr int E = E_;
   static constexpr int TT = L / E;
   static constexpr int RW = RW_;
   static constexpr int NT = TT * RW;
@@ -438,8 +438,7 @@ __device__ __forceinline__ void mirror_vals(const cx<T> (&v)[E], cx<T> (&m)[E], 
 // inside the row's wave.
 template <typename T, int N, int E>
 __device__ __forceinline__ void c2r_row(cx<T> (&v)[E], cx<T>* lds, int t, int row) {
-  using Z = ZP<T, N>;
-  static_assert(E == Z::E, "row register count");
+  using Z = ZP<T, N, ZDefaultRows<N>::value, E>;
   constexpr int L = Z::L, TT = Z::TT;
   cx<T> mr[E];
   mirror_vals<T, TT, E>(v, mr, t);
@@ -467,8 +466,7 @@ __device__ __forceinline__ void c2r_row(cx<T> (&v)[E], cx<T>* lds, int t, int ro
 // packed Y[k] (slot 0 = X0 + i X_{n/2}).
 template <typename T, int N, int E>
 __device__ __forceinline__ void r2c_row(cx<T> (&v)[E], cx<T>* lds, int t, int row) {
-  using Z = ZP<T, N>;
-  static_assert(E == Z::E, "row register count");
+  using Z = ZP<T, N, ZDefaultRows<N>::value, E>;
   constexpr int L = Z::L, TT = Z::TT;
   fft<T, L, E, false, 1, Z::PITCH, true>(v, lds, t, row);
   cx<T> mr[E];
@@ -506,12 +504,12 @@ __device__ __forceinline__ void r2c_row(cx<T> (&v)[E], cx<T>* lds, int t, int ro
 // the last to the first (the y pass before it ends at the last rows, whose
 // output is then still in the last-level cache).  PRE = 3 loads all three
 // rows up front; PRE = 1 loads each before its use (fewer registers).
-template <typename T, int N, int RW, int PRE_, int OCC>
-__global__ void TG_BOUNDS((ZP<T, N, RW>::NT), OCC)
+template <typename T, int N, int RW, int PRE_, int OCC, int EZ>
+__global__ void TG_BOUNDS((ZP<T, N, RW, EZ>::NT), OCC)
 k_z_matvec(cx<T>* __restrict__ V1, cx<T>* __restrict__ V2, cx<T>* __restrict__ V3,
            const T* __restrict__ m, long long m_bs, const ProbScalars* __restrict__ sc, int pred,
            int rev, int blk0) {
-  using Z = ZP<T, N, RW>;
+  using Z = ZP<T, N, RW, EZ>;
   constexpr int E = Z::E, TT = Z::TT;
   __shared__ cx<T> lds[Z::RW * Z::PITCH];
   const int b = blockIdx.y;

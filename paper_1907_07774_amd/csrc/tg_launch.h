@@ -100,18 +100,22 @@ struct SLaunch {
   }
 };
 
-template <typename T, int N, int RW, int OCC>
+// z-pass launches.  The matvec kernel takes RW rows per workgroup and EZ
+// complex values per lane (L/EZ lanes per row); the time-step kernels use
+// the default lanes per row.
+template <typename T, int N, int RW, int OCC, int EZ = FftE<N / 2>::value>
 struct ZLaunch {
   using Z = ZP<T, N, RW>;
+  using ZM = ZP<T, N, RW * EZ / FftE<N / 2>::value, EZ>;  // same threads, EZ per lane
   static void z_matvec(cx<T>* V1, cx<T>* V2, cx<T>* V3, const T* m, long long m_bs,
                        const ProbScalars* sc, int pred, int rev, int nb, int k, int nslab,
                        hipStream_t st) {
-    const int nbk = Z::NBLK / nslab;
+    const int nbk = ZM::NBLK / nslab;
     // FP32 holds all three rows unless an occupancy floor asks for fewer
     // registers; FP64 always streams them one at a time.
     constexpr int PRE = (sizeof(T) == 4 && OCC < 4) ? 3 : 1;
-    k_z_matvec<T, N, RW, PRE, OCC><<<dim3(nbk, nb), Z::NT, 0, st>>>(V1, V2, V3, m, m_bs, sc, pred,
-                                                                     rev, k * nbk);
+    k_z_matvec<T, N, ZM::RW, PRE, OCC, EZ><<<dim3(nbk, nb), ZM::NT, 0, st>>>(
+        V1, V2, V3, m, m_bs, sc, pred, rev, k * nbk);
   }
   template <int MODE>
   static void zs(const ZArgs& a, int nb, hipStream_t st) {
@@ -136,6 +140,7 @@ struct ZLaunch {
     s.z_matvec = &z_matvec;
     s.z_step = &z_step;
   }
+  static void fill_matvec(Sched<T, N>& s) { s.z_matvec = &z_matvec; }
 };
 
 // Candidate tile shapes.  Pencils per x/y workgroup: 8, 16, 32 (row
@@ -178,6 +183,21 @@ template <typename T, int N>
 bool set_zrows(Sched<T, N>& s, int waves, int occ) {
   if (occ == 4) return set_zrows_occ<T, N, 4>(s, waves);
   if (occ == 1) return set_zrows_occ<T, N, 1>(s, waves);
+  return false;
+}
+
+// Matvec z pass with half the default values per lane (twice the lanes per
+// row: full 128-byte row segments per load instruction at n = 256), on
+// workgroups of one wave.
+template <typename T, int N>
+bool set_zmatvec_wide(Sched<T, N>& s, int occ) {
+  constexpr int E0 = FftE<N / 2>::value;
+  constexpr int L = N / 2;
+  if constexpr (E0 >= 8 && (L / (E0 / 2)) <= 64) {
+    constexpr int r1 = 64 / (L / E0);
+    if (occ == 4) { ZLaunch<T, N, r1, 4, E0 / 2>::fill_matvec(s); return true; }
+    if (occ == 1) { ZLaunch<T, N, r1, 1, E0 / 2>::fill_matvec(s); return true; }
+  }
   return false;
 }
 

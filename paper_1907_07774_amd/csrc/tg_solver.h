@@ -70,10 +70,14 @@ class Solver final : public ISolver {
     if (occ == 0) occ = 1;
     if (slabs != 1 && slabs != 2 && slabs != 4 && slabs != 8) return false;
     if (!set_strided<T, N>(s, C, occ)) return false;
-    if (!set_zrows<T, N>(s, zwaves, occ)) {
+    // zwaves 8: one-wave z workgroups whose matvec kernel uses twice the
+    // lanes per row (see set_zmatvec_wide)
+    const bool wide = zwaves == 8;
+    if (!set_zrows<T, N>(s, wide ? 1 : zwaves, occ)) {
       if (!set_zrows<T, N>(s, 1, occ)) return false;
       zwaves = 1;
     }
+    if (wide && !set_zmatvec_wide<T, N>(s, occ)) return false;
     if (s.sy_nblk % slabs != 0 || s.z_nblk % slabs != 0) return false;
     sch_ = s;
     zwaves_ = zwaves;
