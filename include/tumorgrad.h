@@ -153,9 +153,10 @@ tg_status tg_plan_get_schedule(const tg_plan* plan, int* pencils, int* z_waves, 
 tg_status tg_stats(tg_plan* plan, tg_solve_stats* out);
 
 /* Kernel timer for performance measurement.  Identifies one kernel of the
- * PCG iteration (1: x-pass inverse with direction update, 2: y-pass inverse,
- * 3: z-pass C2R * m * R2C, 4: y-pass forward, 5: x-pass forward with
- * q = p - dt/2 A p, 6: PCG vector update; 0: off).  While enabled, every
+ * PCG iteration (1: x-pass inverse with direction update and |p|^2,
+ * 2: y-pass inverse, 3: z-pass C2R * m * R2C with the m |grad p|^2 sum,
+ * 4: y-pass forward, 5: x-pass forward with the iterate and residual
+ * update; 0: off).  While enabled, every
  * launch of that kernel is bracketed by HIP events on the plan's stream.
  * tg_kernel_timer resets the counters. */
 tg_status tg_kernel_timer(tg_plan* plan, int kernel_id);
@@ -166,8 +167,8 @@ tg_status tg_kernel_timer(tg_plan* plan, int kernel_id);
 tg_status tg_kernel_timer_read(tg_plan* plan, double* total_ms, long long* launches,
                                double* work_bytes);
 
-/* Batched gradient evaluation as one replayable HIP graph (SURVEY-style
- * "many problems in one launch"): for each plan, forward + misfit + adjoint
+/* Batched gradient evaluation as one replayable HIP graph (many problems
+ * in one launch): for each plan, forward + misfit + adjoint
  * (tg_forward then tg_adjoint_misfit) on that plan's batch of problems, all
  * captured on `stream` into one graph.  Inside the graph every PCG solve
  * runs a fixed, predicated iteration budget (kernels of converged problems

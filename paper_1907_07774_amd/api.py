@@ -195,7 +195,7 @@ class Plan:
         return tuple(x.value for x in v)
 
     KERNELS = {"x_inv_grad": 1, "y_inv_grad": 2, "z_matvec": 3, "y_fwd_div": 4,
-               "x_fwd_div": 5, "pcg_update": 6}
+               "x_fwd_div": 5}
 
     def kernel_timer(self, name: str | None):
         """Bracket every launch of one PCG-iteration kernel with HIP events."""

@@ -49,8 +49,8 @@ size_t layout(const tg_plan& p, char* base, tg::Workspace* w) {
     off += align_up(bytes);
     return ptr;
   };
-  for (int i = 0; i < 8; ++i) w->spec[i] = take(spec * d.batch);
-  for (int i = 0; i < 8; ++i) w->dspec[i] = d.dirs > 0 ? take(spec * d.dirs) : nullptr;
+  for (int i = 0; i < tg::NSPEC; ++i) w->spec[i] = take(spec * d.batch);
+  for (int i = 0; i < tg::NSPEC; ++i) w->dspec[i] = d.dirs > 0 ? take(spec * d.dirs) : nullptr;
   w->ck = take(real * d.batch * d.nseg);
   w->ckb = take(real * d.batch * d.nseg);
   w->segc = take(real * d.batch * d.s);
@@ -237,7 +237,7 @@ tg_status tg_stats(tg_plan* plan, tg_solve_stats* out) {
 }
 
 tg_status tg_kernel_timer(tg_plan* plan, int kernel_id) {
-  if (plan == nullptr || kernel_id < tg::KT_NONE || kernel_id > tg::KT_PCG_UPDATE) return TG_ERR_ARG;
+  if (plan == nullptr || kernel_id < tg::KT_NONE || kernel_id > tg::KT_LAST) return TG_ERR_ARG;
   if (!plan->solver) return TG_ERR_WORKSPACE;
   return from_hip(plan->solver->timer_enable(kernel_id));
 }

@@ -178,8 +178,22 @@ __device__ __forceinline__ void lds_sync() {
   }
 }
 
-// LDS addressing: element (position p, column c) lives at lds[p*PS + c*CS].
-template <typename T, int L, int E, bool INV, int PS, int CS, int Ns, bool WAVE = false>
+// LDS addressing: element (position p, column c) lives at lds[p*PS + c*CS],
+// or with PAD at lds[p + p/E + c*CS] (PS = 1): one spare slot after every E
+// positions, so the first stage's stride-E writes from the lanes of a row
+// fall in distinct banks (the row pitch CS must be at least L + L/E).
+template <typename T, int L, int E, int PS, int CS, bool PAD>
+__device__ __forceinline__ int lds_at(int p, int col) {
+  if constexpr (PAD) {
+    static_assert(PS == 1 && CS >= L + L / E, "padded layout is for contiguous rows");
+    return p + p / E + col * CS;
+  } else {
+    return p * PS + col * CS;
+  }
+}
+
+template <typename T, int L, int E, bool INV, int PS, int CS, int Ns, bool WAVE = false,
+          bool PAD = false>
 struct Stockham {
   static __device__ __forceinline__ void run(cx<T> (&v)[E], cx<T>* lds, int t, int col) {
     constexpr int R = (L / Ns >= E) ? E : (L / Ns);
@@ -207,23 +221,39 @@ struct Stockham {
         const int j = t + b * TT;
         const int k = j & (Ns - 1);
         const int base = (j / Ns) * Ns * R + k;
+        if constexpr (PAD && Ns == 1 && R == E) {
+          // positions j E + r: padded index j (E + 1) + r
+          const int wb = t * (E + 1) + col * CS;
 #pragma unroll
-        for (int r = 0; r < R; ++r) lds[(base + r * Ns) * PS + col * CS] = v[b + r * NB];
+          for (int r = 0; r < R; ++r) lds[wb + b * TT * (E + 1) + r] = v[b + r * NB];
+        } else {
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+            lds[lds_at<T, L, E, PS, CS, PAD>(base + r * Ns, col)] = v[b + r * NB];
+        }
       }
       lds_sync<WAVE>();
+      if constexpr (PAD) {
+        // positions t + e TT with t < TT: padded index t + t/E + e TT + (e TT)/E
+        static_assert(E % TT == 0 || TT % E == 0, "padded read needs E | TT or TT | E");
+        const int rb = t + t / E + col * CS;
 #pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = lds[(t + e * TT) * PS + col * CS];
+        for (int e = 0; e < E; ++e) v[e] = lds[rb + e * TT + (e * TT) / E];
+      } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = lds[lds_at<T, L, E, PS, CS, PAD>(t + e * TT, col)];
+      }
       lds_sync<WAVE>();
-      Stockham<T, L, E, INV, PS, CS, Ns * R, WAVE>::run(v, lds, t, col);
+      Stockham<T, L, E, INV, PS, CS, Ns * R, WAVE, PAD>::run(v, lds, t, col);
     }
   }
 };
 
 // Full L-point FFT of the values held by (t, col); in and out mapping:
 // v[e] <-> position t + (L/E) e.
-template <typename T, int L, int E, bool INV, int PS, int CS, bool WAVE = false>
+template <typename T, int L, int E, bool INV, int PS, int CS, bool WAVE = false, bool PAD = false>
 __device__ __forceinline__ void fft(cx<T> (&v)[E], cx<T>* lds, int t, int col) {
-  Stockham<T, L, E, INV, PS, CS, 1, WAVE>::run(v, lds, t, col);
+  Stockham<T, L, E, INV, PS, CS, 1, WAVE, PAD>::run(v, lds, t, col);
 }
 
 // Elements-per-thread choice for an L-point transform.

@@ -37,7 +37,8 @@ struct ProbScalars {
 enum : int { STAT_NOT_CONVERGED = 1, STAT_BREAKDOWN = 2, STAT_NONFINITE = 4 };
 
 constexpr int NSLOT = 4;      // simultaneous partial sums per reducing kernel
-constexpr int MAXBLK = 8192;  // max workgroups of a reducing kernel per problem
+constexpr int MAXBLK = 16384;  // max workgroups of a reducing kernel per problem
+constexpr int NSPEC = 7;       // spectral work fields per problem
 
 struct SolverDims {
   int n, nt, n_p, batch, dirs, s, nseg;
@@ -47,8 +48,8 @@ struct SolverDims {
 
 // Views into the caller-provided workspace.
 struct Workspace {
-  void* spec[8];      // X, R, P, Q, T1, T2, T3, S: [batch][n^3/2] complex
-  void* dspec[8];     // the same set for Hessian directions: [dirs][n^3/2]
+  void* spec[NSPEC];  // X, R, P, T1, T2, T3, S: [batch][n^3/2] complex
+  void* dspec[NSPEC]; // the same set for Hessian directions: [dirs][n^3/2]
   void* ck;           // [nseg][batch][n^3] checkpoints c^{j s}
   void* ckb;          // [nseg][batch][n^3] b^{j s - 1} (j >= 1)
   void* segc;         // [s][batch][n^3]  c^n within the live segment
@@ -102,7 +103,7 @@ enum KernelId : int {
   KT_Z_MATVEC = 3,
   KT_Y_FWD_DIV = 4,
   KT_X_FWD_DIV = 5,
-  KT_PCG_UPDATE = 6
+  KT_LAST = KT_X_FWD_DIV
 };
 
 // Phi^T partial-block count for grid size n (workspace sizing).

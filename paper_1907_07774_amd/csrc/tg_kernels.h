@@ -116,13 +116,16 @@ struct SP {
   const long long base = (long long)b * S::SPEC + S::colbase(gc);
 
 // ---- x pass, inverse, gradient prologue of the diffusion matvec.
-// MODE 0: p is given.  MODE 1: PCG direction p = M r + beta p (stored).
+// MODE 0: p is given.  MODE 1: PCG direction p = M r + beta p (stored) and
+// partial |p|^2 (slot 0; Parseval weights).
 // Out: U1 = IFFT_x(s i wx p), U2 = IFFT_x(s p), s = 1/n^3.
 template <typename T, int N, int C, int MODE, int OCC>
 __global__ void TG_BOUNDS((SP<T, N, C, 0>::NT), OCC)
 k_x_inv_grad(cx<T>* __restrict__ P, const cx<T>* __restrict__ Rr, cx<T>* __restrict__ U1,
-             cx<T>* __restrict__ U2, const ProbScalars* __restrict__ sc, double tau, int pred) {
+             cx<T>* __restrict__ U2, const ProbScalars* __restrict__ sc, double* __restrict__ part,
+             double tau, int pred) {
   SP_SETUP(0)
+  __shared__ double red[MODE == 1 ? NSLOT * ((S::NT + 63) / 64) : 1];
   if (pred && sc[b].done) return;
   const int ky = gc / NH, kz = gc % NH;
   const T wy = (T)wfull<N>(ky), wz = (T)kz;
@@ -132,6 +135,7 @@ k_x_inv_grad(cx<T>* __restrict__ P, const cx<T>* __restrict__ Rr, cx<T>* __restr
     const bool first = sc[b].first != 0;
     const T beta = (T)sc[b].beta;
     const T kb = (T)(tau * sc[b].kbar);
+    double pp = 0.0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int kx = t + TT * e;
@@ -142,7 +146,11 @@ k_x_inv_grad(cx<T>* __restrict__ P, const cx<T>* __restrict__ Rr, cx<T>* __restr
       if (!first) p = p + scale(P[o], beta);
       P[o] = p;
       v[e] = p;
+      pp += (double)p.x * (double)p.x + (double)p.y * (double)p.y;
     }
+    double acc[NSLOT] = {(kz == 0 ? 1.0 : 2.0) * pp, 0.0, 0.0, 0.0};
+    block_sums<S::NT>(acc, 1, red);
+    if (threadIdx.x == 0) part_at(part, b, 0)[blockIdx.x] = acc[0];
   } else {
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = P[base + (t + TT * e) * S::PSTR];
@@ -227,7 +235,7 @@ k_y_fwd_div(cx<T>* __restrict__ H1, cx<T>* __restrict__ H2, const cx<T>* __restr
 // ---- x pass, forward, divergence epilogue of the diffusion matvec:
 // Am = i wx FFT_x(W1) + FFT_x(W23) is the spectrum of div(m grad u).
 enum XMode : int {
-  XM_PCG = 0,      // q = p - tau kf Am; partial <p, q>
+  XM_PCG = 0,      // q = p - tau kf Am; x += alpha p; r -= alpha q; partials <r, M r>, |r|^2
   XM_RHS_FWD = 1,  // x0 = X; r = 2 tau kf Am; partials |rhs|^2, <r, M r>, |r|^2
   XM_RHS_ADJ = 2,  // x0 = X; r = tau kf Am;  rhs = X
   XM_POST_ADJ = 3  // X += tau kf Am; partial <Am, S> (k_f gradient)
@@ -256,16 +264,27 @@ k_x_fwd_div(const cx<T>* __restrict__ W1, const cx<T>* __restrict__ W23, cx<T>* 
   double acc[NSLOT] = {0.0, 0.0, 0.0, 0.0};
   int ns = 0;
   if constexpr (MODE == XM_PCG) {
-    ns = 1;
+    // X: iterate x, Q: residual r, Sv: direction p; alpha is already known
+    // (from |p|^2 and the z pass's sum of m |grad p|^2), so the update
+    // happens here and q = A p never goes to memory.
+    ns = 2;
+    const T al = (T)sc[b].alpha;
+    const T kb = (T)(tau * sc[b].kbar);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int kx = t + TT * e;
       const long long o = base + kx * S::PSTR;
-      const cx<T> am = mul_i(a[e], (T)wfull<N>(kx)) + c[e];
-      const cx<T> p = X[o];
+      const T wx = (T)wfull<N>(kx);
+      const cx<T> am = mul_i(a[e], wx) + c[e];
+      const cx<T> p = Sv[o];
       const cx<T> q = p - scale(am, tk);
-      Q[o] = q;
-      acc[0] += wgt * ((double)p.x * (double)q.x + (double)p.y * (double)q.y);
+      X[o] = X[o] + scale(p, al);
+      const cx<T> r = Q[o] - scale(q, al);
+      Q[o] = r;
+      const T pre = T(1) / (T(1) + kb * (wx * wx + wy * wy + wz * wz));
+      const double rr = (double)r.x * (double)r.x + (double)r.y * (double)r.y;
+      acc[0] += wgt * (double)pre * rr;
+      acc[1] += wgt * rr;
     }
   } else if constexpr (MODE == XM_RHS_FWD || MODE == XM_RHS_ADJ) {
     ns = 3;
@@ -386,8 +405,8 @@ k_x_fwd_state(const cx<T>* __restrict__ H, cx<T>* __restrict__ X, cx<T>* __restr
 
 // ------------------------------------------------------------- z passes
 // Rows (b, x, y) of n reals = n/2 complex.  RW rows per workgroup; thread
-// (t, row) holds complex positions t + TT e.  LDS row pitch L + TT spreads
-// the rows of a wave over the banks.
+// (t, row) holds complex positions t + TT e.  LDS rows use the padded
+// layout (one spare slot per E positions), pitch L + TT.
 template <int N>
 struct ZDefaultRows {
   static constexpr int L = N / 2;
@@ -459,7 +478,7 @@ __device__ __forceinline__ void c2r_row(cx<T> (&v)[E], cx<T>* lds, int t, int ro
     }
   }
   (void)L;
-  fft<T, L, E, true, 1, Z::PITCH, true>(v, lds, t, row);
+  fft<T, L, E, true, 1, Z::PITCH, true, true>(v, lds, t, row);
 }
 
 // Unnormalized R2C of one row: in v[e] = x[2j] + i x[2j+1]; out v[e] =
@@ -468,7 +487,7 @@ template <typename T, int N, int E>
 __device__ __forceinline__ void r2c_row(cx<T> (&v)[E], cx<T>* lds, int t, int row) {
   using Z = ZP<T, N, ZDefaultRows<N>::value, E>;
   constexpr int L = Z::L, TT = Z::TT;
-  fft<T, L, E, false, 1, Z::PITCH, true>(v, lds, t, row);
+  fft<T, L, E, false, 1, Z::PITCH, true, true>(v, lds, t, row);
   cx<T> mr[E];
   mirror_vals<T, TT, E>(v, mr, t);
 #pragma unroll
@@ -504,14 +523,20 @@ __device__ __forceinline__ void r2c_row(cx<T> (&v)[E], cx<T>* lds, int t, int ro
 // the last to the first (the y pass before it ends at the last rows, whose
 // output is then still in the last-level cache).  PRE = 3 loads all three
 // rows up front; PRE = 1 loads each before its use (fewer registers).
+// Each workgroup also leaves the partial sum of m |grad u|^2 over its rows
+// in slot 1 (per lane and row an FP32 sum of 32
+// products, then FP64): with |u|^2 this gives <u, A u> of the Crank-Nicolson
+// operator, because the spectral divergence is minus the adjoint of the
+// spectral gradient.
 template <typename T, int N, int RW, int PRE_, int OCC, int EZ>
 __global__ void TG_BOUNDS((ZP<T, N, RW, EZ>::NT), OCC)
 k_z_matvec(cx<T>* __restrict__ V1, cx<T>* __restrict__ V2, cx<T>* __restrict__ V3,
-           const T* __restrict__ m, long long m_bs, const ProbScalars* __restrict__ sc, int pred,
-           int rev, int blk0) {
+           const T* __restrict__ m, long long m_bs, const ProbScalars* __restrict__ sc,
+           double* __restrict__ part, int pred, int rev, int blk0) {
   using Z = ZP<T, N, RW, EZ>;
   constexpr int E = Z::E, TT = Z::TT;
   __shared__ cx<T> lds[Z::RW * Z::PITCH];
+  __shared__ double red[NSLOT * ((Z::NT + 63) / 64)];
   const int b = blockIdx.y;
   if (pred && sc[b].done) return;
   const int t = threadIdx.x % TT, row = threadIdx.x / TT;
@@ -524,6 +549,7 @@ k_z_matvec(cx<T>* __restrict__ V1, cx<T>* __restrict__ V2, cx<T>* __restrict__ V
   // PRE = 3 keeps m in registers for all three rows; PRE = 1 re-reads the
   // m row (a cache hit after the first row) to save registers.
   cx<T> mv[PRE == 3 ? E : 1], v[PRE][E];
+  double mg = 0.0;
   if constexpr (PRE == 3) {
 #pragma unroll
     for (int e = 0; e < E; ++e) mv[e] = mrow[t + TT * e];
@@ -544,11 +570,18 @@ k_z_matvec(cx<T>* __restrict__ V1, cx<T>* __restrict__ V2, cx<T>* __restrict__ V
       for (int e = 0; e < E; ++e) u[e] = mul_i(u[e], (T)(t + TT * e));
     }
     c2r_row<T, N>(u, lds, t, row);
+    T sj = T(0);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const cx<T> me = PRE == 3 ? mv[PRE == 3 ? e : 0] : mrow[t + TT * e];
-      u[e] = mk(u[e].x * me.x, u[e].y * me.y);
+      const cx<T> g = u[e];
+      u[e] = mk(g.x * me.x, g.y * me.y);
+      sj += g.x * u[e].x + g.y * u[e].y;
     }
+    mg += (double)sj;
+    // pin the sum here: left alone, the compiler sinks it to its use at the
+    // end of the kernel and keeps its inputs live through all three rows
+    asm volatile("" : "+v"(mg));
     r2c_row<T, N>(u, lds, t, row);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -556,6 +589,9 @@ k_z_matvec(cx<T>* __restrict__ V1, cx<T>* __restrict__ V2, cx<T>* __restrict__ V
       Vs[j][t + TT * e] = u[e];
     }
   }
+  double acc[NSLOT] = {mg, 0.0, 0.0, 0.0};
+  block_sums<Z::NT>(acc, 1, red);
+  if (threadIdx.x == 0) part_at(part, b, 1)[bx] = acc[0];
 }
 
 // ---- time-step boundary kernels (reaction halves fused around the
@@ -737,56 +773,10 @@ __global__ void __launch_bounds__((ZP<T, N, RW>::NT)) k_z_step(ZArgs a) {
   }
 }
 
-// --------------------------------------------------- pointwise spectral
-template <typename T, int N>
-struct PW {
-  static constexpr int NT = 256;
-  static constexpr long long SPEC = (long long)N * N * (N / 2);
-  static constexpr int NBLK = (SPEC / NT / 8) < 1024 ? (int)((SPEC / NT / 8) > 0 ? SPEC / NT / 8 : 1) : 1024;
-};
-
-// x += alpha p; r -= alpha q; partials <r, M r>, |r|^2.
-template <typename T, int N>
-__global__ void __launch_bounds__(256)
-k_pcg_update(cx<T>* __restrict__ X, cx<T>* __restrict__ R, const cx<T>* __restrict__ P,
-             const cx<T>* __restrict__ Q, const ProbScalars* __restrict__ sc,
-             double* __restrict__ part, double tau) {
-  using W = PW<T, N>;
-  __shared__ double red[NSLOT * 4];
-  const int b = blockIdx.y;
-  if (sc[b].done) return;
-  constexpr int NH = N / 2;
-  const T al = (T)sc[b].alpha;
-  const T kb = (T)(tau * sc[b].kbar);
-  const long long off = (long long)b * W::SPEC;
-  double acc[NSLOT] = {0.0, 0.0, 0.0, 0.0};
-  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < W::SPEC;
-       i += (long long)gridDim.x * 256) {
-    const int kz = (int)(i % NH);
-    const int ky = (int)((i / NH) % N);
-    const int kx = (int)(i / ((long long)NH * N));
-    const T wx = (T)wfull<N>(kx), wy = (T)wfull<N>(ky), wz = (T)kz;
-    const T pre = T(1) / (T(1) + kb * (wx * wx + wy * wy + wz * wz));
-    const double wgt = kz == 0 ? 1.0 : 2.0;
-    const long long o = off + i;
-    X[o] = X[o] + scale(P[o], al);
-    const cx<T> r = R[o] - scale(Q[o], al);
-    R[o] = r;
-    const double rr = (double)r.x * (double)r.x + (double)r.y * (double)r.y;
-    acc[0] += wgt * (double)pre * rr;
-    acc[1] += wgt * rr;
-  }
-  block_sums<256>(acc, 2, red);
-  if (threadIdx.x == 0) {
-    part_at(part, b, 0)[blockIdx.x] = acc[0];
-    part_at(part, b, 1)[blockIdx.x] = acc[1];
-  }
-}
-
 // ---------------------------------------------------------- finalizers
 enum FinMode : int {
   FIN_INIT = 0,   // slots: |rhs|^2, <r,Mr>, |r|^2
-  FIN_PQ = 1,     // slot: <p,q>
+  FIN_PAP = 1,    // slots: |p|^2 (nblk), sum m |grad p|^2 (nblk2) -> <p, A p>, alpha
   FIN_RZ = 2,     // slots: <r,Mr>, |r|^2
   FIN_GRHO = 3,   // slot: g_rho increment
   FIN_GK = 4,     // slot: spectral <Am mu, s>
@@ -797,12 +787,12 @@ enum FinMode : int {
 template <int MODE>
 __global__ void __launch_bounds__(256)
 k_finalize(ProbScalars* __restrict__ sc, const double* __restrict__ part, int nblk,
-           double scale_, double rtol, int maxit) {
+           double scale_, double rtol, int maxit, int nblk2 = 0) {
   __shared__ double red[NSLOT * 4];
   const int b = blockIdx.x;
   ProbScalars& S = sc[b];
-  if ((MODE == FIN_PQ || MODE == FIN_RZ) && S.done) return;
-  constexpr int ns = MODE == FIN_INIT ? 3 : MODE == FIN_RZ ? 2 : 1;
+  if ((MODE == FIN_PAP || MODE == FIN_RZ) && S.done) return;
+  constexpr int ns = MODE == FIN_INIT ? 3 : (MODE == FIN_RZ || MODE == FIN_PAP) ? 2 : 1;
   double acc[NSLOT] = {0.0, 0.0, 0.0, 0.0};
   if constexpr (MODE == FIN_MMAX) {
     double mx = 0.0;
@@ -818,8 +808,10 @@ k_finalize(ProbScalars* __restrict__ sc, const double* __restrict__ part, int nb
     }
     return;
   }
-  for (int s = 0; s < ns; ++s)
-    for (int i = threadIdx.x; i < nblk; i += 256) acc[s] += part_at((double*)part, b, s)[i];
+  for (int s = 0; s < ns; ++s) {
+    const int nb = (MODE == FIN_PAP && s == 1) ? nblk2 : nblk;
+    for (int i = threadIdx.x; i < nb; i += 256) acc[s] += part_at((double*)part, b, s)[i];
+  }
   block_sums<256>(acc, ns, red);
   if (threadIdx.x != 0) return;
   if constexpr (MODE == FIN_INIT) {
@@ -839,16 +831,19 @@ k_finalize(ProbScalars* __restrict__ sc, const double* __restrict__ part, int nb
       const double rel = S.rhs2 > 0 ? sqrt(S.rr / S.rhs2) : 0.0;
       S.worst = fmax(S.worst, rel);
     }
-  } else if constexpr (MODE == FIN_PQ) {
-    S.pq = acc[0];
-    if (!(acc[0] > 0.0) || !isfinite(acc[0])) {
-      S.status |= isfinite(acc[0]) ? STAT_BREAKDOWN : STAT_NONFINITE;
+  } else if constexpr (MODE == FIN_PAP) {
+    // spectral sums: <p, A p> = sum w |p|^2 + tau k_f n^3 sum_x m |grad p|^2
+    // (scale_ = tau n^3)
+    const double pap = acc[0] + scale_ * S.kf * acc[1];
+    S.pq = pap;
+    if (!(pap > 0.0) || !isfinite(pap)) {
+      S.status |= isfinite(pap) ? STAT_BREAKDOWN : STAT_NONFINITE;
       S.done = 1;
       S.alpha = 0.0;
       const double rel = S.rhs2 > 0 ? sqrt(S.rr / S.rhs2) : 0.0;
       S.worst = fmax(S.worst, rel);
     } else {
-      S.alpha = S.rho / acc[0];
+      S.alpha = S.rho / pap;
     }
   } else if constexpr (MODE == FIN_RZ) {
     const double rho_new = acc[0];

@@ -12,9 +12,11 @@ struct Sched {
   int RW = 0;      // rows per z workgroup
   int sx_nblk = 0; // x-pass workgroups per problem (partial-sum count)
   int z_nblk = 0;  // z-pass workgroups per problem (partial-sum count)
+  int zm_nblk = 0; // z matvec workgroups per problem (partial-sum count)
   int sy_nblk = 0; // y-pass workgroups per problem
   void (*x_inv_grad)(int mode, cx<T>* P, const cx<T>* R, cx<T>* U1, cx<T>* U2,
-                     const ProbScalars* sc, double tau, int pred, int nb, hipStream_t st) = nullptr;
+                     const ProbScalars* sc, double* part, double tau, int pred, int nb,
+                     hipStream_t st) = nullptr;
   // y-pass and z-pass launches over slab k of nslab (x-plane ranges)
   void (*y_inv_grad)(cx<T>* U1, cx<T>* U2, cx<T>* V3, const ProbScalars* sc, int pred, int nb,
                      int k, int nslab, hipStream_t st) = nullptr;
@@ -28,8 +30,8 @@ struct Sched {
   void (*x_fwd_state)(const cx<T>* H, cx<T>* X, cx<T>* U1, cx<T>* U2, cx<T>* S2, int nb,
                       hipStream_t st) = nullptr;
   void (*z_matvec)(cx<T>* V1, cx<T>* V2, cx<T>* V3, const T* m, long long m_bs,
-                   const ProbScalars* sc, int pred, int rev, int nb, int k, int nslab,
-                   hipStream_t st) = nullptr;
+                   const ProbScalars* sc, double* part, int pred, int rev, int nb, int k,
+                   int nslab, hipStream_t st) = nullptr;
   void (*z_step)(int mode, const ZArgs& a, int nb, hipStream_t st) = nullptr;
 };
 
@@ -37,12 +39,16 @@ template <typename T, int N, int C, int OCC>
 struct SLaunch {
   using SX = SP<T, N, C, 0>;
   using SY = SP<T, N, C, 1>;
+  static_assert(SX::NBLK <= MAXBLK, "x-pass partial sums exceed the partial buffer");
   static void x_inv_grad(int mode, cx<T>* P, const cx<T>* R, cx<T>* U1, cx<T>* U2,
-                         const ProbScalars* sc, double tau, int pred, int nb, hipStream_t st) {
+                         const ProbScalars* sc, double* part, double tau, int pred, int nb,
+                         hipStream_t st) {
     if (mode == 1)
-      k_x_inv_grad<T, N, C, 1, OCC><<<dim3(SX::NBLK, nb), SX::NT, 0, st>>>(P, R, U1, U2, sc, tau, pred);
+      k_x_inv_grad<T, N, C, 1, OCC><<<dim3(SX::NBLK, nb), SX::NT, 0, st>>>(P, R, U1, U2, sc, part,
+                                                                           tau, pred);
     else
-      k_x_inv_grad<T, N, C, 0, OCC><<<dim3(SX::NBLK, nb), SX::NT, 0, st>>>(P, R, U1, U2, sc, tau, pred);
+      k_x_inv_grad<T, N, C, 0, OCC><<<dim3(SX::NBLK, nb), SX::NT, 0, st>>>(P, R, U1, U2, sc, part,
+                                                                           tau, pred);
   }
   static void y_inv_grad(cx<T>* U1, cx<T>* U2, cx<T>* V3, const ProbScalars* sc, int pred, int nb,
                          int k, int nslab, hipStream_t st) {
@@ -107,15 +113,16 @@ template <typename T, int N, int RW, int OCC, int EZ = FftE<N / 2>::value>
 struct ZLaunch {
   using Z = ZP<T, N, RW>;
   using ZM = ZP<T, N, RW * EZ / FftE<N / 2>::value, EZ>;  // same threads, EZ per lane
+  static_assert(ZM::NBLK <= MAXBLK && Z::NBLK <= MAXBLK, "z-pass partial sums exceed the buffer");
   static void z_matvec(cx<T>* V1, cx<T>* V2, cx<T>* V3, const T* m, long long m_bs,
-                       const ProbScalars* sc, int pred, int rev, int nb, int k, int nslab,
-                       hipStream_t st) {
+                       const ProbScalars* sc, double* part, int pred, int rev, int nb, int k,
+                       int nslab, hipStream_t st) {
     const int nbk = ZM::NBLK / nslab;
     // FP32 holds all three rows unless an occupancy floor asks for fewer
     // registers; FP64 always streams them one at a time.
     constexpr int PRE = (sizeof(T) == 4 && OCC < 4) ? 3 : 1;
     k_z_matvec<T, N, ZM::RW, PRE, OCC, EZ><<<dim3(nbk, nb), ZM::NT, 0, st>>>(
-        V1, V2, V3, m, m_bs, sc, pred, rev, k * nbk);
+        V1, V2, V3, m, m_bs, sc, part, pred, rev, k * nbk);
   }
   template <int MODE>
   static void zs(const ZArgs& a, int nb, hipStream_t st) {
@@ -137,10 +144,14 @@ struct ZLaunch {
   static void fill(Sched<T, N>& s) {
     s.RW = RW;
     s.z_nblk = Z::NBLK;
+    s.zm_nblk = ZM::NBLK;
     s.z_matvec = &z_matvec;
     s.z_step = &z_step;
   }
-  static void fill_matvec(Sched<T, N>& s) { s.z_matvec = &z_matvec; }
+  static void fill_matvec(Sched<T, N>& s) {
+    s.zm_nblk = ZM::NBLK;
+    s.z_matvec = &z_matvec;
+  }
 };
 
 // Candidate tile shapes.  Pencils per x/y workgroup: 8, 16, 32 (row

@@ -29,7 +29,6 @@ namespace tg {
 
 template <typename T, int N>
 class Solver final : public ISolver {
-  using W = PW<T, N>;
   using RPc = RP<T, N>;
   using PT = PhiT<T, N>;
   static constexpr long long REAL = (long long)N * N * N;
@@ -37,7 +36,7 @@ class Solver final : public ISolver {
 
   // A batch of independent PCG systems sharing one launch.
   struct Ctx {
-    cx<T>* X; cx<T>* R; cx<T>* P; cx<T>* Q; cx<T>* T1; cx<T>* T2; cx<T>* T3; cx<T>* S;
+    cx<T>* X; cx<T>* R; cx<T>* P; cx<T>* T1; cx<T>* T2; cx<T>* T3; cx<T>* S;
     ProbScalars* sc;
     double* part;
     int nb;
@@ -235,8 +234,8 @@ class Solver final : public ISolver {
   Ctx prim() {
     Ctx c;
     cx<T>** sp = (cx<T>**)w_.spec;
-    c.X = sp[0]; c.R = sp[1]; c.P = sp[2]; c.Q = sp[3];
-    c.T1 = sp[4]; c.T2 = sp[5]; c.T3 = sp[6]; c.S = sp[7];
+    c.X = sp[0]; c.R = sp[1]; c.P = sp[2];
+    c.T1 = sp[3]; c.T2 = sp[4]; c.T3 = sp[5]; c.S = sp[6];
     c.sc = w_.sc; c.part = w_.part; c.nb = d_.batch;
     c.m = m_; c.m_bs = REAL; c.traj_bs = REAL;
     return c;
@@ -244,8 +243,8 @@ class Solver final : public ISolver {
   Ctx dirs(int ndir) {
     Ctx c;
     cx<T>** sp = (cx<T>**)w_.dspec;
-    c.X = sp[0]; c.R = sp[1]; c.P = sp[2]; c.Q = sp[3];
-    c.T1 = sp[4]; c.T2 = sp[5]; c.T3 = sp[6]; c.S = sp[7];
+    c.X = sp[0]; c.R = sp[1]; c.P = sp[2];
+    c.T1 = sp[3]; c.T2 = sp[4]; c.T3 = sp[5]; c.S = sp[6];
     c.sc = w_.sc + d_.batch;
     c.part = w_.part + (size_t)d_.batch * NSLOT * MAXBLK;
     c.nb = ndir;
@@ -291,6 +290,7 @@ class Solver final : public ISolver {
   // matvec middle (y inverse, z, y forward) on U1, U2 (V3 scratch); the
   // three passes run slab by slab over nslab x-plane ranges so each slab's
   // intermediates can stay in the last-level cache between passes.
+  // The z pass also leaves the partial sums of m |grad u|^2 (slot 1).
   void matvec_mid(const Ctx& c, cx<T>* U1, cx<T>* U2, cx<T>* V3, int pred) {
     const int work = pred ? 0 : c.nb;
     const int ns = nslab_;
@@ -299,7 +299,7 @@ class Solver final : public ISolver {
         sch_.y_inv_grad(U1, U2, V3, c.sc, pred, c.nb, k, ns, st_);
       });
       timed(KT_Z_MATVEC, k == 0 ? work : 0, [&] {
-        sch_.z_matvec(U1, U2, V3, c.m, c.m_bs, c.sc, pred, 1, c.nb, k, ns, st_);
+        sch_.z_matvec(U1, U2, V3, c.m, c.m_bs, c.sc, c.part, pred, 1, c.nb, k, ns, st_);
       });
       timed(KT_Y_FWD_DIV, k == 0 ? work : 0, [&] {
         sch_.y_fwd_div(U1, U2, V3, c.sc, pred, c.nb, k, ns, st_);
@@ -339,21 +339,22 @@ class Solver final : public ISolver {
     return d_.rtol;
   }
 
+  // One PCG iteration (Sec. 3.3: Crank-Nicolson system, Fourier
+  // preconditioner).  alpha = <r, M r> / <p, A p> with <p, A p> = |p|^2 +
+  // tau k_f |sqrt(m) grad p|^2 (partials from the x and z passes), so the
+  // last x pass applies x += alpha p and r -= alpha A p directly.
   void pcg_iteration(const Ctx& c) {
     timed(KT_X_INV_GRAD, 0, [&] {
-      sch_.x_inv_grad(1, c.P, c.R, c.T1, c.T2, c.sc, tau_, 1, c.nb, st_);
+      sch_.x_inv_grad(1, c.P, c.R, c.T1, c.T2, c.sc, c.part, tau_, 1, c.nb, st_);
     });
     matvec_mid(c, c.T1, c.T2, c.T3, 1);
+    k_finalize<FIN_PAP><<<c.nb, 256, 0, st_>>>(c.sc, c.part, sch_.sx_nblk, tau_ * (double)REAL,
+                                               rtol(), maxit(), sch_.zm_nblk);
     timed(KT_X_FWD_DIV, 0, [&] {
-      sch_.x_fwd_div(XM_PCG, c.T1, c.T2, c.P, c.Q, nullptr, c.sc, c.part, tau_, 1, 0, c.nb, st_);
+      sch_.x_fwd_div(XM_PCG, c.T1, c.T2, c.X, c.R, c.P, c.sc, c.part, tau_, 1, 0, c.nb, st_);
     });
-    k_finalize<FIN_PQ><<<c.nb, 256, 0, st_>>>(c.sc, c.part, sch_.sx_nblk, 1.0 / REAL, rtol(),
+    k_finalize<FIN_RZ><<<c.nb, 256, 0, st_>>>(c.sc, c.part, sch_.sx_nblk, 1.0 / REAL, rtol(),
                                               maxit());
-    timed(KT_PCG_UPDATE, 0, [&] {
-      k_pcg_update<T, N><<<dim3(W::NBLK, c.nb), 256, 0, st_>>>(c.X, c.R, c.P, c.Q, c.sc, c.part,
-                                                               tau_);
-    });
-    k_finalize<FIN_RZ><<<c.nb, 256, 0, st_>>>(c.sc, c.part, W::NBLK, 1.0 / REAL, rtol(), maxit());
   }
 
   // ------------------------------------------------------ kernel timer
@@ -368,8 +369,7 @@ class Solver final : public ISolver {
       case KT_Y_INV_GRAD: return 5 * S;   // read U1, U2; write V1, V2, V3
       case KT_Z_MATVEC: return 7 * S;     // read V1..V3, m; write H1..H3
       case KT_Y_FWD_DIV: return 5 * S;    // read H1..H3; write W1, W23
-      case KT_X_FWD_DIV: return 4 * S;    // read W1, W23, p; write q
-      case KT_PCG_UPDATE: return 6 * S;   // read x, r, p, q; write x, r
+      case KT_X_FWD_DIV: return 7 * S;    // read W1, W23, p, x, r; write x, r
     }
     return 0.0;
   }
@@ -544,7 +544,7 @@ class Solver final : public ISolver {
         }
         TG_CHECK(step_solve(c, true));
         // lam_a = mu + tau k_f A_m mu; g_k += tau <A_m mu, a + b>
-        sch_.x_inv_grad(0, c.X, nullptr, c.T1, c.T2, c.sc, tau_, 0, c.nb, st_);
+        sch_.x_inv_grad(0, c.X, nullptr, c.T1, c.T2, c.sc, nullptr, tau_, 0, c.nb, st_);
         matvec_mid(c, c.T1, c.T2, c.T3, 0);
         sch_.x_fwd_div(XM_POST_ADJ, c.T1, c.T2, c.X, nullptr, c.S, c.sc, c.part, tau_, 0,
                        gn ? 0 : 1, c.nb, st_);

@@ -69,9 +69,9 @@ def test_plan_create_and_workspace_size():
     assert st == _lib.TG_OK
     nb = C.c_size_t()
     assert L.tg_plan_workspace_bytes(h, C.byref(nb)) == _lib.TG_OK
-    # 8 spectra + 8 direction spectra + checkpoint/segment fields, FP64
+    # 7 spectra, 7 spectra per direction, checkpoints, segment, adjoint; FP64
     field = 32 ** 3 * 8
-    assert nb.value >= (16 + 2 + 2 + 4 + 4 + 2) * field
+    assert nb.value >= (7 + 7 * 2 + 2 + 2 + 4 + 4 + 2) * field
     # unbound plan: calls fail on the host without touching a GPU
     assert L.tg_forward(h, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), C.c_void_p(8),
                         C.c_void_p(8), None) == _lib.TG_ERR_WORKSPACE
