@@ -27,6 +27,7 @@ EXPORTS = (
     "tg_vjp", "tg_adjoint_misfit", "tg_hessvec_gn", "tg_stats",
     "tg_status_string", "tg_plan_destroy", "tg_version", "tg_kernel_timer",
     "tg_kernel_timer_read", "tg_plan_set_schedule", "tg_plan_get_schedule",
+    "tg_plan_set_pass", "tg_plan_get_pass",
     "tg_batch_capture", "tg_batch_launch", "tg_batch_destroy",
 )
 
@@ -94,10 +95,13 @@ def lib():
     L.tg_plan_set_schedule.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int]
     L.tg_plan_get_schedule.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                        C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    L.tg_plan_set_pass.argtypes = [vp, C.c_int, C.c_int, C.c_int]
+    L.tg_plan_get_pass.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
     for name in ("tg_plan_create", "tg_plan_workspace_bytes", "tg_plan_bind", "tg_forward",
                  "tg_vjp", "tg_adjoint_misfit", "tg_hessvec_gn", "tg_stats",
                  "tg_kernel_timer", "tg_kernel_timer_read", "tg_plan_set_schedule",
-                 "tg_plan_get_schedule", "tg_batch_capture", "tg_batch_launch"):
+                 "tg_plan_get_schedule", "tg_plan_set_pass", "tg_plan_get_pass",
+                 "tg_batch_capture", "tg_batch_launch"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L

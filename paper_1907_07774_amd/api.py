@@ -43,7 +43,7 @@ class Plan:
     def __init__(self, n: int, nt: int, centres, sigma: float, T: float = 1.0,
                  rtol: float = 1e-8, maxit: int = 1000, ckpt_stride: int = 0,
                  precision: str = "fp64", batch: int = 1, max_hvp_dirs: int = 0,
-                 device: str | torch.device = "cuda:0", schedule=None):
+                 device: str | torch.device = "cuda:0", schedule=None, passes=None):
         L = _lib.lib()
         cen = np.asarray(centres, dtype=np.float64)
         if cen.ndim == 2:
@@ -71,6 +71,8 @@ class Plan:
         self.workspace_bytes = int(nbytes.value)
         self._ws = None
         self._schedule = schedule
+        self._passes_req = dict(passes or {})
+        self._passes = {}
         self._keep = ()
         self.generation = 0
 
@@ -84,14 +86,18 @@ class Plan:
             self._ws = ws
             _lib.check(_lib.lib().tg_plan_bind(self._h, C.c_void_p(ws.data_ptr() + off),
                                                 self.workspace_bytes), "tg_plan_bind")
+            passes = self._passes_req
             if self._schedule is not None:
                 self.set_schedule(*self._schedule)
             else:
                 from . import autotune
-                sch = autotune.lookup(autotune.gpu_arch(self.device), self.n, self.precision,
+                ent = autotune.lookup(autotune.gpu_arch(self.device), self.n, self.precision,
                                       self.batch)
-                if sch is not None:
-                    self.set_schedule(*sch)
+                if ent is not None:
+                    self.set_schedule(*ent[0])
+                    passes = {**ent[1], **passes}
+            for k, (c, o) in passes.items():
+                self.set_pass(k, c, o)
 
     def _stream(self):
         return C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
@@ -186,6 +192,7 @@ class Plan:
         _lib.check(_lib.lib().tg_plan_set_schedule(self._h, int(pencils), int(z_waves),
                                                     int(slabs), int(waves_per_simd)),
                    "tg_plan_set_schedule")
+        self._passes = {}
 
     def get_schedule(self):
         self._bind()
@@ -196,6 +203,20 @@ class Plan:
 
     KERNELS = {"x_inv_grad": 1, "y_inv_grad": 2, "z_matvec": 3, "y_fwd_div": 4,
                "x_fwd_div": 5}
+
+    def set_pass(self, kernel: str, pencils: int, waves_per_simd: int):
+        """Tile shape of one PCG pass (after set_schedule); pencils 0 for z_matvec."""
+        self._bind()
+        _lib.check(_lib.lib().tg_plan_set_pass(self._h, self.KERNELS[kernel], int(pencils),
+                                                int(waves_per_simd)), "tg_plan_set_pass")
+        self._passes[kernel] = (int(pencils), int(waves_per_simd))
+
+    def get_pass(self, kernel: str):
+        self._bind()
+        c, o = C.c_int(), C.c_int()
+        _lib.check(_lib.lib().tg_plan_get_pass(self._h, self.KERNELS[kernel], C.byref(c),
+                                                C.byref(o)), "tg_plan_get_pass")
+        return c.value, o.value
 
     def kernel_timer(self, name: str | None):
         """Bracket every launch of one PCG-iteration kernel with HIP events."""

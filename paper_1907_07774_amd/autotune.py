@@ -1,16 +1,20 @@
 """Autotuner for the transform tile shapes.
 
-The x/y passes take C pencils per workgroup (C in 8, 16, 32) and the z pass
-takes 1, 2 or 4 waves of rows per workgroup.  ``tune`` times one forward
-solve of a plan for every candidate pair and keeps the fastest; results are
-cached per (GPU architecture, grid size, precision, batch) in a JSON file.
-Plans created through ``api.Plan`` apply the cached choice when they bind.
+Plan-wide knobs: pencils per x/y workgroup (8, 16, 32), waves of rows per
+z workgroup (1, 2, 4; 8 = one-wave workgroups with twice the lanes per row
+in the z matvec), x slabs of the y-z-y chain (1, 2, 4, 8) and an occupancy
+floor (1 or 4 waves per SIMD).  ``tune`` times one forward solve of a plan
+for every plan-wide candidate and keeps the fastest; ``tune_passes`` then
+gives each PCG pass its own (pencils, occupancy) by timing that pass alone
+with the plan's HIP-event kernel timer, and keeps the result only if the
+whole forward solve gets faster.  Results are cached per (GPU architecture,
+grid size, precision, batch class) in a JSON file; plans created through
+``api.Plan`` apply the cached choice when they bind.
 """
 from __future__ import annotations
 
 import json
 import os
-import time
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(PKG, "schedules.json")
@@ -18,6 +22,9 @@ PENCILS = (8, 16, 32)
 Z_WAVES = (1, 2, 4, 8)
 SLABS = (1, 2, 4, 8)
 OCCUPANCY = (1, 4)
+# PCG passes with their own tile shape, with the field volumes each moves
+# per problem (for the achieved-bandwidth report)
+PASSES = {"x_inv_grad": 5, "y_inv_grad": 5, "z_matvec": 7, "y_fwd_div": 5, "x_fwd_div": 7}
 
 
 def cache_path() -> str:
@@ -39,11 +46,14 @@ def load(path: str | None = None) -> dict:
 
 
 def lookup(arch: str, n: int, precision: str, batch: int):
+    """((pencils, z_waves, slabs, waves_per_simd), {pass: (pencils, waves)}) or None."""
     ent = load().get(key(arch, n, precision, batch))
     if not ent:
         return None
-    return (int(ent["pencils"]), int(ent["z_waves"]), int(ent.get("slabs", 1)),
-            int(ent.get("waves_per_simd", 1)))
+    sch = (int(ent["pencils"]), int(ent["z_waves"]), int(ent.get("slabs", 1)),
+           int(ent.get("waves_per_simd", 1)))
+    passes = {k: (int(v[0]), int(v[1])) for k, v in ent.get("passes", {}).items()}
+    return sch, passes
 
 
 def gpu_arch(device) -> str:
@@ -52,34 +62,89 @@ def gpu_arch(device) -> str:
     return getattr(props, "gcnArchName", "unknown").split(":")[0]
 
 
-def tune(plan, p, rho_f, k_f, m, reps: int = 2, candidates=None, verbose: bool = False):
-    """Time plan.forward for every (pencils, z_waves, slabs, waves_per_simd)
-    candidate; set and return the fastest with the table of timings (ms)."""
+def _time_forward(plan, args, reps):
     import torch
+    st = torch.cuda.current_stream(plan.device)
+    plan.forward(*args)  # warm-up (also fixes the PCG chunking)
+    torch.cuda.synchronize(plan.device)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        plan.forward(*args)
+    e1.record(st)
+    torch.cuda.synchronize(plan.device)
+    return e0.elapsed_time(e1) / reps
+
+
+def tune(plan, p, rho_f, k_f, m, reps: int = 2, candidates=None, verbose: bool = False):
+    """Time plan.forward for every plan-wide (pencils, z_waves, slabs,
+    waves_per_simd) candidate; set and return the fastest with the table of
+    timings (ms)."""
     cands = candidates or [(c, w, s, o) for c in PENCILS for w in Z_WAVES for s in SLABS
                            for o in OCCUPANCY]
     times = {}
-    st = torch.cuda.current_stream(plan.device)
     for cand in cands:
         try:
             plan.set_schedule(*cand)
         except Exception:
             continue
-        plan.forward(p, rho_f, k_f, m)  # warm-up (also fixes the PCG chunking)
-        torch.cuda.synchronize(plan.device)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(st)
-        for _ in range(reps):
-            plan.forward(p, rho_f, k_f, m)
-        e1.record(st)
-        torch.cuda.synchronize(plan.device)
-        times[cand] = e0.elapsed_time(e1) / reps
+        times[cand] = _time_forward(plan, (p, rho_f, k_f, m), reps)
         if verbose:
             print(f"  schedule {cand}: {times[cand]:.2f} ms", flush=True)
     best = min(times, key=times.get)
     plan.set_schedule(*best)
     return best, times
+
+
+def _pass_time(plan, args, name):
+    """ms per launch that did work, from the kernel timer (one forward)."""
+    plan.kernel_timer(name)
+    plan.forward(*args)
+    ms, _launches, work_bytes = plan.kernel_timer_read()
+    plan.kernel_timer(None)
+    unit = PASSES[name] * plan.n ** 3 * (4 if plan.precision == "fp32" else 8)
+    work = work_bytes / unit
+    return ms / work if work > 0 else float("inf")
+
+
+def tune_passes(plan, p, rho_f, k_f, m, reps: int = 2, verbose: bool = False):
+    """Per-pass (pencils, waves_per_simd) on top of the plan's current
+    schedule.  Returns (passes, forward ms before, forward ms after); the
+    plan keeps the per-pass choice only if the forward solve got faster."""
+    args = (p, rho_f, k_f, m)
+    base = _time_forward(plan, args, reps)
+    zw = plan.get_schedule()[1]
+    chosen = {}
+    for name in PASSES:
+        if name == "z_matvec":
+            opts = [] if zw == 8 else [(0, o) for o in OCCUPANCY]
+        else:
+            opts = [(c, o) for c in PENCILS for o in OCCUPANCY]
+        cur = plan.get_pass(name)
+        best, best_t = cur, _pass_time(plan, args, name)
+        for opt in opts:
+            if opt == cur:
+                continue
+            try:
+                plan.set_pass(name, *opt)
+            except Exception:
+                continue
+            t = _pass_time(plan, args, name)
+            if verbose:
+                print(f"  pass {name} {opt}: {t * 1e3:.1f} us", flush=True)
+            if t < best_t:
+                best, best_t = opt, t
+        plan.set_pass(name, *best)
+        chosen[name] = best
+        if verbose:
+            print(f"  pass {name} -> {best} ({best_t * 1e3:.1f} us)", flush=True)
+    after = _time_forward(plan, args, reps)
+    if after >= base:
+        sch = plan.get_schedule()
+        plan.set_schedule(*sch)  # back to the plan-wide shapes
+        return {}, base, after
+    return chosen, base, after
 
 
 def store(entries: dict, path: str | None = None) -> None:

@@ -94,6 +94,9 @@ class ISolver {
   // Largest PCG iteration count of one solve seen since the last forward.
   virtual int its_max_last_call() const = 0;
   virtual void get_schedule(int* C, int* zwaves, int* slabs, int* occ) const = 0;
+  // Per-pass override of the tile shape after set_schedule (KT_* id).
+  virtual bool set_pass(int id, int C, int occ) = 0;
+  virtual bool get_pass(int id, int* C, int* occ) const = 0;
 };
 
 enum KernelId : int {

@@ -6,14 +6,21 @@
 
 namespace tg {
 
+// The four x/y passes of the PCG matvec (x_inv_grad, y_inv_grad, y_fwd_div,
+// x_fwd_div) and the z matvec can each take their own tile shape; the
+// remaining transform kernels use the plan-wide pencil count C.
 template <typename T, int N>
 struct Sched {
-  int C = 0;       // pencils per x/y workgroup
+  int C = 0;       // pencils per x/y workgroup of the other transform kernels
   int RW = 0;      // rows per z workgroup
-  int sx_nblk = 0; // x-pass workgroups per problem (partial-sum count)
+  int sx_nblk = 0; // x-pass workgroups per problem at C
   int z_nblk = 0;  // z-pass workgroups per problem (partial-sum count)
   int zm_nblk = 0; // z matvec workgroups per problem (partial-sum count)
-  int sy_nblk = 0; // y-pass workgroups per problem
+  int sy_nblk = 0; // y-pass workgroups per problem at C
+  int xi_nblk = 0; // x_inv_grad workgroups (partial-sum count)
+  int xf_nblk = 0; // x_fwd_div workgroups (partial-sum count)
+  int yi_nblk = 0; // y_inv_grad workgroups
+  int yf_nblk = 0; // y_fwd_div workgroups
   void (*x_inv_grad)(int mode, cx<T>* P, const cx<T>* R, cx<T>* U1, cx<T>* U2,
                      const ProbScalars* sc, double* part, double tau, int pred, int nb,
                      hipStream_t st) = nullptr;
@@ -92,14 +99,20 @@ struct SLaunch {
                           hipStream_t st) {
     k_x_fwd_state<T, N, C><<<dim3(SX::NBLK, nb), SX::NT, 0, st>>>(H, X, U1, U2, S2);
   }
+  // one PCG pass (KT_X_INV_GRAD, KT_Y_INV_GRAD, KT_Y_FWD_DIV, KT_X_FWD_DIV)
+  static void fill_pass(Sched<T, N>& s, int id) {
+    switch (id) {
+      case KT_X_INV_GRAD: s.x_inv_grad = &x_inv_grad; s.xi_nblk = SX::NBLK; break;
+      case KT_Y_INV_GRAD: s.y_inv_grad = &y_inv_grad; s.yi_nblk = SY::NBLK; break;
+      case KT_Y_FWD_DIV: s.y_fwd_div = &y_fwd_div; s.yf_nblk = SY::NBLK; break;
+      case KT_X_FWD_DIV: s.x_fwd_div = &x_fwd_div; s.xf_nblk = SX::NBLK; break;
+    }
+  }
   static void fill(Sched<T, N>& s) {
     s.C = C;
     s.sx_nblk = SX::NBLK;
     s.sy_nblk = SY::NBLK;
-    s.x_inv_grad = &x_inv_grad;
-    s.y_inv_grad = &y_inv_grad;
-    s.y_fwd_div = &y_fwd_div;
-    s.x_fwd_div = &x_fwd_div;
+    for (int id : {KT_X_INV_GRAD, KT_Y_INV_GRAD, KT_Y_FWD_DIV, KT_X_FWD_DIV}) fill_pass(s, id);
     s.x_inv = &x_inv;
     s.y_plain = &y_plain;
     s.x_fwd_state = &x_fwd_state;
@@ -156,44 +169,62 @@ struct ZLaunch {
 
 // Candidate tile shapes.  Pencils per x/y workgroup: 8, 16, 32 (row
 // segments of 64..512 bytes).  Rows per z workgroup: one, two or four waves.
+// pass < 0: every x/y kernel; else one PCG pass (KT_* id).
 template <typename T, int N, int OCC>
-bool set_strided_occ(Sched<T, N>& s, int C) {
+bool set_strided_occ(Sched<T, N>& s, int C, int pass) {
   switch (C) {
-    case 8: SLaunch<T, N, 8, OCC>::fill(s); return true;
-    case 16: SLaunch<T, N, 16, OCC>::fill(s); return true;
-    case 32: SLaunch<T, N, 32, OCC>::fill(s); return true;
+    case 8:
+      if (pass < 0) SLaunch<T, N, 8, OCC>::fill(s); else SLaunch<T, N, 8, OCC>::fill_pass(s, pass);
+      return true;
+    case 16:
+      if (pass < 0) SLaunch<T, N, 16, OCC>::fill(s); else SLaunch<T, N, 16, OCC>::fill_pass(s, pass);
+      return true;
+    case 32:
+      if (pass < 0) SLaunch<T, N, 32, OCC>::fill(s); else SLaunch<T, N, 32, OCC>::fill_pass(s, pass);
+      return true;
   }
   return false;
 }
 
 // occ: occupancy floor in waves per SIMD (1: none, 4: at least four)
 template <typename T, int N>
-bool set_strided(Sched<T, N>& s, int C, int occ) {
-  if (occ == 4) return set_strided_occ<T, N, 4>(s, C);
-  if (occ == 1) return set_strided_occ<T, N, 1>(s, C);
+bool set_strided(Sched<T, N>& s, int C, int occ, int pass = -1) {
+  if (occ == 4) return set_strided_occ<T, N, 4>(s, C, pass);
+  if (occ == 1) return set_strided_occ<T, N, 1>(s, C, pass);
   return false;
 }
 
+// matvec_only: replace only the z matvec kernel (its occupancy floor)
 template <typename T, int N, int OCC>
-bool set_zrows_occ(Sched<T, N>& s, int waves) {
+bool set_zrows_occ(Sched<T, N>& s, int waves, bool matvec_only) {
   constexpr int TT = ZP<T, N>::TT;
   constexpr int r1 = 64 / TT;
   switch (waves) {
-    case 1: ZLaunch<T, N, r1, OCC>::fill(s); return true;
+    case 1:
+      if (matvec_only) ZLaunch<T, N, r1, OCC>::fill_matvec(s); else ZLaunch<T, N, r1, OCC>::fill(s);
+      return true;
     case 2:
-      if constexpr (N * N >= 2 * r1) { ZLaunch<T, N, 2 * r1, OCC>::fill(s); return true; }
+      if constexpr (N * N >= 2 * r1) {
+        if (matvec_only) ZLaunch<T, N, 2 * r1, OCC>::fill_matvec(s);
+        else ZLaunch<T, N, 2 * r1, OCC>::fill(s);
+        return true;
+      }
       return false;
     case 4:
-      if constexpr (N * N >= 4 * r1) { ZLaunch<T, N, 4 * r1, OCC>::fill(s); return true; }
+      if constexpr (N * N >= 4 * r1) {
+        if (matvec_only) ZLaunch<T, N, 4 * r1, OCC>::fill_matvec(s);
+        else ZLaunch<T, N, 4 * r1, OCC>::fill(s);
+        return true;
+      }
       return false;
   }
   return false;
 }
 
 template <typename T, int N>
-bool set_zrows(Sched<T, N>& s, int waves, int occ) {
-  if (occ == 4) return set_zrows_occ<T, N, 4>(s, waves);
-  if (occ == 1) return set_zrows_occ<T, N, 1>(s, waves);
+bool set_zrows(Sched<T, N>& s, int waves, int occ, bool matvec_only = false) {
+  if (occ == 4) return set_zrows_occ<T, N, 4>(s, waves, matvec_only);
+  if (occ == 1) return set_zrows_occ<T, N, 1>(s, waves, matvec_only);
   return false;
 }
 

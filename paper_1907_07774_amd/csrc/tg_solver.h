@@ -77,11 +77,15 @@ class Solver final : public ISolver {
       zwaves = 1;
     }
     if (wide && !set_zmatvec_wide<T, N>(s, occ)) return false;
-    if (s.sy_nblk % slabs != 0 || s.z_nblk % slabs != 0) return false;
+    if (!slabs_fit(s, slabs)) return false;
     sch_ = s;
     zwaves_ = zwaves;
     nslab_ = slabs;
     occ_ = occ;
+    for (int id = 1; id <= KT_LAST; ++id) {
+      pass_C_[id] = id == KT_Z_MATVEC ? 0 : C;
+      pass_occ_[id] = occ;
+    }
     return true;
   }
   void get_schedule(int* C, int* zwaves, int* slabs, int* occ) const override {
@@ -89,6 +93,29 @@ class Solver final : public ISolver {
     *zwaves = zwaves_;
     *slabs = nslab_;
     *occ = occ_;
+  }
+  // Tile shape of one PCG pass (KT_* id): pencils for the x/y passes (0
+  // for the z matvec) and its occupancy floor.
+  bool set_pass(int id, int C, int occ) override {
+    if (id < 1 || id > KT_LAST) return false;
+    Sched<T, N> s = sch_;
+    if (id == KT_Z_MATVEC) {
+      if (C != 0 || zwaves_ == 8) return false;
+      if (!set_zrows<T, N>(s, zwaves_, occ, true)) return false;
+    } else {
+      if (!set_strided<T, N>(s, C, occ, id)) return false;
+    }
+    if (!slabs_fit(s, nslab_)) return false;
+    sch_ = s;
+    pass_C_[id] = C;
+    pass_occ_[id] = occ;
+    return true;
+  }
+  bool get_pass(int id, int* C, int* occ) const override {
+    if (id < 1 || id > KT_LAST) return false;
+    *C = pass_C_[id];
+    *occ = pass_occ_[id];
+    return true;
   }
 
   // ------------------------------------------------------------ forward
@@ -320,7 +347,7 @@ class Solver final : public ISolver {
     sch_.x_fwd_div(adj ? XM_RHS_ADJ : XM_RHS_FWD, c.T2, c.T3, c.X, c.R, nullptr, c.sc, c.part, tau_,
                    0, 0, c.nb, st_);
     TG_LAUNCH_CHECK();
-    k_finalize<FIN_INIT><<<c.nb, 256, 0, st_>>>(c.sc, c.part, sch_.sx_nblk, 1.0 / REAL, rtol(),
+    k_finalize<FIN_INIT><<<c.nb, 256, 0, st_>>>(c.sc, c.part, sch_.xf_nblk, 1.0 / REAL, rtol(),
                                                 maxit());
     TG_LAUNCH_CHECK();
     return pcg_loop(c);
@@ -348,12 +375,12 @@ class Solver final : public ISolver {
       sch_.x_inv_grad(1, c.P, c.R, c.T1, c.T2, c.sc, c.part, tau_, 1, c.nb, st_);
     });
     matvec_mid(c, c.T1, c.T2, c.T3, 1);
-    k_finalize<FIN_PAP><<<c.nb, 256, 0, st_>>>(c.sc, c.part, sch_.sx_nblk, tau_ * (double)REAL,
+    k_finalize<FIN_PAP><<<c.nb, 256, 0, st_>>>(c.sc, c.part, sch_.xi_nblk, tau_ * (double)REAL,
                                                rtol(), maxit(), sch_.zm_nblk);
     timed(KT_X_FWD_DIV, 0, [&] {
       sch_.x_fwd_div(XM_PCG, c.T1, c.T2, c.X, c.R, c.P, c.sc, c.part, tau_, 1, 0, c.nb, st_);
     });
-    k_finalize<FIN_RZ><<<c.nb, 256, 0, st_>>>(c.sc, c.part, sch_.sx_nblk, 1.0 / REAL, rtol(),
+    k_finalize<FIN_RZ><<<c.nb, 256, 0, st_>>>(c.sc, c.part, sch_.xf_nblk, 1.0 / REAL, rtol(),
                                               maxit());
   }
 
@@ -550,7 +577,7 @@ class Solver final : public ISolver {
                        gn ? 0 : 1, c.nb, st_);
         TG_LAUNCH_CHECK();
         if (!gn) {
-          k_finalize<FIN_GK><<<c.nb, 256, 0, st_>>>(c.sc, c.part, sch_.sx_nblk, tau_ / REAL, 0, 0);
+          k_finalize<FIN_GK><<<c.nb, 256, 0, st_>>>(c.sc, c.part, sch_.xf_nblk, tau_ / REAL, 0, 0);
           TG_LAUNCH_CHECK();
         }
       }
@@ -605,6 +632,12 @@ class Solver final : public ISolver {
   int zwaves_ = 0;
   int nslab_ = 1;
   int occ_ = 1;
+  int pass_C_[KT_LAST + 1] = {};
+  int pass_occ_[KT_LAST + 1] = {};
+  static bool slabs_fit(const Sched<T, N>& s, int slabs) {
+    return s.yi_nblk % slabs == 0 && s.yf_nblk % slabs == 0 && s.zm_nblk % slabs == 0 &&
+           s.z_nblk % slabs == 0;
+  }
   ProbScalars* stat_sc_ = nullptr;
   int stat_nb_ = 0;
   // kernel timer state

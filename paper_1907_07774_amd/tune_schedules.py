@@ -14,7 +14,7 @@ import torch
 from . import api, autotune, inputs
 
 
-def tune_case(n, precision, batch, nt, seed, verbose=True, candidates=None):
+def tune_case(n, precision, batch, nt, seed, verbose=True, candidates=None, per_pass=True):
     probs = [inputs.problem(n, 2 if n <= 64 else 4, seed + b, nt=nt) for b in range(batch)]
     cen = np.stack([q.centres for q in probs])
     plan = api.Plan(n, nt, cen, probs[0].sigma, rtol=1e-8, precision=precision, batch=batch,
@@ -28,10 +28,18 @@ def tune_case(n, precision, batch, nt, seed, verbose=True, candidates=None):
     if verbose:
         print(f"tuning n={n} {precision} batch={batch} nt={nt}", flush=True)
     best, times = autotune.tune(plan, p, rho, kf, m, verbose=verbose, candidates=candidates)
+    passes, before, after = ({}, times[best], times[best])
+    if per_pass:
+        passes, before, after = autotune.tune_passes(plan, p, rho, kf, m, verbose=verbose)
+        if verbose:
+            print(f"  per-pass shapes: {before:.2f} -> {after:.2f} ms "
+                  f"({'kept' if passes else 'dropped'})", flush=True)
     arch = autotune.gpu_arch(dev)
     k = autotune.key(arch, n, precision, batch)
     ent = {"pencils": best[0], "z_waves": best[1], "slabs": best[2],
-           "waves_per_simd": best[3] if len(best) > 3 else 1, "ms": times[best],
+           "waves_per_simd": best[3] if len(best) > 3 else 1,
+           "ms": min(after, times[best]) if passes else times[best],
+           "passes": {name: list(v) for name, v in passes.items()},
            "table_ms": {"x".join(map(str, k)): round(t, 4) for k, t in times.items()}}
     del plan
     torch.cuda.empty_cache()
@@ -46,6 +54,8 @@ def main(argv=None):
     ap.add_argument("--nt", type=int, default=4)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--no-passes", action="store_true",
+                    help="skip the per-pass refinement")
     ap.add_argument("--candidates", default=None,
                     help="comma-separated pencils x z_waves x slabs x waves_per_simd, "
                          "e.g. 16x1x1x1,32x1x1x4")
@@ -56,9 +66,11 @@ def main(argv=None):
     entries = {}
     for n in a.n:
         for prec in a.precision:
-            k, ent = tune_case(n, prec, a.batch, a.nt, a.seed, candidates=cands)
+            k, ent = tune_case(n, prec, a.batch, a.nt, a.seed, candidates=cands,
+                               per_pass=not a.no_passes)
             entries[k] = ent
             print(f"{k}: pencils={ent['pencils']} z_waves={ent['z_waves']} slabs={ent['slabs']} "
+                  f"waves_per_simd={ent['waves_per_simd']} passes={ent['passes']} "
                   f"({ent['ms']:.2f} ms)", flush=True)
     autotune.store(entries, a.out)
     return 0

@@ -86,6 +86,19 @@ def test_plan_create_and_workspace_size():
     L.tg_plan_destroy(h)
 
 
+def test_schedule_calls_need_a_bound_plan():
+    L = _lib.lib()
+    st, h = create(n=32, nt=4)
+    assert st == _lib.TG_OK
+    c, o = C.c_int(), C.c_int()
+    assert L.tg_plan_set_schedule(h, 16, 1, 1, 1) == _lib.TG_ERR_WORKSPACE
+    assert L.tg_plan_set_pass(h, 1, 16, 1) == _lib.TG_ERR_WORKSPACE
+    assert L.tg_plan_get_pass(h, 1, C.byref(c), C.byref(o)) == _lib.TG_ERR_WORKSPACE
+    assert L.tg_plan_set_pass(None, 1, 16, 1) == _lib.TG_ERR_ARG
+    assert L.tg_plan_get_pass(h, 1, None, C.byref(o)) == _lib.TG_ERR_ARG
+    L.tg_plan_destroy(h)
+
+
 def test_fp32_workspace_is_half_of_fp64():
     L = _lib.lib()
     sizes = []
