@@ -53,10 +53,31 @@ template <> struct TwTab<float> {
   static __device__ __forceinline__ cx<float> get(int k) { return g_tw32[k]; }
 };
 
-// exp(-+ 2 pi i k / M) for M dividing TW_N
+// Per-workgroup LDS copy of the table.  Every kernel that runs an FFT calls
+// tw_fill() once, with all its threads, before its first transform; the
+// per-stage twiddle reads then go to LDS instead of through the vector
+// memory pipeline (where, reloaded for every transform, they outnumbered
+// the data loads several times over).
+// The LDS copy holds the TW_LDS-th roots (every TW_N / TW_LDS-th entry),
+// enough for transforms up to the largest grid, n = 256.
+constexpr int TW_LDS = 256;
+template <typename T>
+__device__ __forceinline__ cx<T>* tw_lds() {
+  __shared__ cx<T> s[TW_LDS];
+  return s;
+}
+template <typename T>
+__device__ __forceinline__ void tw_fill() {
+  cx<T>* s = tw_lds<T>();
+  for (int i = threadIdx.x; i < TW_LDS; i += blockDim.x) s[i] = TwTab<T>::get(i * (TW_N / TW_LDS));
+  __syncthreads();
+}
+
+// exp(-+ 2 pi i k / M) for M dividing TW_LDS
 template <typename T, bool INV, int M>
 __device__ __forceinline__ cx<T> twiddle(int k) {
-  cx<T> w = TwTab<T>::get((k * (TW_N / M)) & (TW_N - 1));
+  static_assert(M <= TW_LDS && TW_LDS % M == 0, "twiddle order exceeds the LDS table");
+  cx<T> w = tw_lds<T>()[(k * (TW_LDS / M)) & (TW_LDS - 1)];
   return INV ? conjg(w) : w;
 }
 

@@ -113,7 +113,8 @@ struct SP {
   const int b = blockIdx.y;                                             \
   const int col = threadIdx.x % C, t = threadIdx.x / C;                 \
   const int gc = ((int)blockIdx.x + (OFF)) * C + col;                   \
-  const long long base = (long long)b * S::SPEC + S::colbase(gc);
+  const long long base = (long long)b * S::SPEC + S::colbase(gc);       \
+  tw_fill<T>();
 
 // ---- x pass, inverse, gradient prologue of the diffusion matvec.
 // MODE 0: p is given.  MODE 1: PCG direction p = M r + beta p (stored) and
@@ -515,7 +516,8 @@ __device__ __forceinline__ void r2c_row(cx<T> (&v)[E], cx<T>* lds, int t, int ro
   const int t = threadIdx.x % TT, row = threadIdx.x / TT;               \
   const long long grow = (long long)blockIdx.x * Z::RW + row;           \
   const long long sbase = (long long)b * Z::SPEC + grow * Z::L;         \
-  (void)sbase;
+  (void)sbase;                                                          \
+  tw_fill<T>();
 
 // ---- matvec core: for j = x, y, z: g_j = C2R(V_j) (V_z times i wz), times
 // m, R2C, (z: times i wz).  In place on V1..V3.  The launch covers the
@@ -539,6 +541,7 @@ k_z_matvec(cx<T>* __restrict__ V1, cx<T>* __restrict__ V2, cx<T>* __restrict__ V
   __shared__ double red[NSLOT * ((Z::NT + 63) / 64)];
   const int b = blockIdx.y;
   if (pred && sc[b].done) return;
+  tw_fill<T>();
   const int t = threadIdx.x % TT, row = threadIdx.x / TT;
   const int bx = blk0 + (rev ? (int)gridDim.x - 1 - (int)blockIdx.x : (int)blockIdx.x);
   const long long grow = (long long)bx * Z::RW + row;
