@@ -23,6 +23,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# field volumes (n^3 elements) each timed PCG kernel reads plus writes per problem
+KERNEL_FIELDS = {"x_inv_grad": 5, "y_inv_grad": 5, "z_matvec": 7, "y_fwd_div": 5, "x_fwd_div": 7}
 METRIC = "fwd+adjoint gradient evals/sec @256³ (FP32-mixed vs FP64) + HBM GB/s"
 
 
@@ -40,7 +42,7 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--timer-kernel", default="z_matvec")
+    ap.add_argument("--timer-kernel", default="z_matvec", choices=sorted(KERNEL_FIELDS))
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     ap.add_argument("--no-batch", action="store_true")
@@ -288,13 +290,20 @@ def main():
     roof = None
     if "timer" in r32:
         t = r32["timer"]
+        # algorithmic bytes of one launch that does work (one problem), and
+        # the achieved rate over every timed launch (predicated launches of
+        # converged problems included, at their ~2 us each)
+        unit = KERNEL_FIELDS[t["kernel"]] * args.n ** 3 * 4
         avg_ms = t["ms"] / max(t["launches"], 1)
         achieved = t["work_bytes"] / (t["ms"] * 1e-3) / 1e9
         traffic = load_traffic(t["kernel"], args.n, "fp32")
         roof = {"bound": "hbm", "kernel": t["kernel"], "achieved": achieved,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                "traffic": traffic, "avg_launch_ms": avg_ms, "launches": t["launches"],
-                "algorithmic_bytes_per_work_launch": t["work_bytes"] / max(t["launches"], 1)}
+                "traffic": traffic, "traffic_unit": "HBM bytes per work launch (rocprofv3 "
+                "FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
+                "avg_launch_ms": avg_ms, "launches": t["launches"],
+                "work_launches": t["work_bytes"] / unit,
+                "algorithmic_bytes_per_work_launch": unit}
 
     out = {
         "metric": METRIC,

@@ -60,6 +60,9 @@ def config2_problem(g):
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
 def test_config2_gradient_128(prec, tol):
+    """The scalar derivatives are sums with cancellation (here |g_rho| is
+    ~1e-3 J / rho_f), so FP32 is held to tol on the log-sensitivity:
+    |theta| |dg| <= tol (|theta g| + J); FP64 to tol relative."""
     print(f"case config2 {prec}", flush=True)
     g = load_golden("config2_128.npz")
     pr, d = config2_problem(g)
@@ -70,8 +73,10 @@ def test_config2_gradient_128(prec, tol):
     assert np.linalg.norm(cT[g["idx"]] - g["cT"]) / np.linalg.norm(g["cT"]) < tol
     assert abs(float(J) - float(g["J"])) < tol * abs(float(g["J"]))
     assert rel(gp.cpu().numpy(), g["g_p"]) < tol
-    assert abs(float(gr) - float(g["g_rho"])) < tol * abs(float(g["g_rho"]))
-    assert abs(float(gk) - float(g["g_k"])) < tol * abs(float(g["g_k"]))
+    for got, ref, theta in ((gr, g["g_rho"], g["rho_f"]), (gk, g["g_k"], g["k_f"])):
+        ref, theta = float(ref), abs(float(theta))
+        scale = abs(ref) if prec == "fp64" else abs(ref) + float(g["J"]) / theta
+        assert abs(float(got) - ref) < tol * scale
 
 
 def test_config2_central_fd_128():
@@ -110,9 +115,14 @@ def bench_problem():
 def test_config3_reaction_only_closed_form_256(bench_problem):
     """k_f = 0 at the benchmark size: c(T) = R_T(Phi p) point by point.
     The path still takes 32 transform round trips.  Their rounding error is
-    absolute (relative to max c) and grows like exp(rho_f m t) where c is
-    tiny, the linearized logistic growth: about 1e-11 in FP64 and 1e-3 in
-    FP32 at such points, so FP32 is held to the relative L2 bound."""
+    absolute (relative to max c, ~1e-16 in FP64 and ~1e-7 in FP32 per trip)
+    and where c is small the logistic flow amplifies it like its
+    linearization, by up to exp(rho_f m T) ~ 2.6e4 here: about 1e-11 in
+    FP64 and up to ~1e-2 in FP32 at such points.  Points that crossed that
+    phase and saturated keep part of it (measured: up to 5e-3 relative at
+    c(T) ~ 0.16).  FP64 is held to 1e-10 absolute everywhere; FP32 to 1e-3
+    relative L2 over the points with c(T) > 0.1 and to the amplified
+    rounding level (2e-2) everywhere."""
     print("case config3 reaction-only", flush=True)
     pr = bench_problem
     idx = np.random.default_rng(7).choice(256 ** 3, 2000, replace=False)
@@ -125,7 +135,10 @@ def test_config3_reaction_only_closed_form_256(bench_problem):
         if prec == "fp64":
             assert np.abs(cT - expect).max() < 1e-10 * max(1.0, np.abs(expect).max())
         else:
-            assert rel(cT, expect) < 1e-4
+            sat = expect > 0.1
+            assert sat.sum() >= 20
+            assert rel(cT[sat], expect[sat]) < 1e-3
+            assert np.abs(cT - expect).max() < 2e-2
         del plan
         torch.cuda.empty_cache()
 
