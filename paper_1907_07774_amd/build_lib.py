@@ -21,7 +21,10 @@ ARCH = "gfx950"
 # Packed FP32 instructions are disabled for all device code.
 DEV_FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC"]
+# The host layers are plain C++ against the HIP runtime API (no device code).
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+HOST_FLAGS = ["-x", "c++", "-O2", "-std=c++17", "-fPIC", "-D__HIP_PLATFORM_AMD__",
+              f"-I{ROCM}/include", "-Wall", "-Werror=unused-result"]
 
 GRIDS = (8, 16, 32, 64, 128, 256)
 # one translation unit per (precision, grid size), plus the host layers

@@ -336,14 +336,14 @@ tg_status tg_batch_capture(int nplans, tg_plan* const* plans, const tg_batch_io*
   hipGraph_t graph = nullptr;
   hipError_t e2 = hipStreamEndCapture(st, &graph);
   if (e != hipSuccess || e2 != hipSuccess) {
-    if (graph) hipGraphDestroy(graph);
+    if (graph) (void)hipGraphDestroy(graph);
     return TG_ERR_HIP;
   }
   tg_batch* bt = new tg_batch;
   bt->graph = graph;
   bt->plans.assign(plans, plans + nplans);
   if (hipGraphInstantiate(&bt->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-    hipGraphDestroy(graph);
+    (void)hipGraphDestroy(graph);
     delete bt;
     return TG_ERR_HIP;
   }
@@ -364,8 +364,8 @@ tg_status tg_batch_launch(tg_batch* batch, void* stream) {
 
 void tg_batch_destroy(tg_batch* batch) {
   if (batch == nullptr) return;
-  if (batch->exec) hipGraphExecDestroy(batch->exec);
-  if (batch->graph) hipGraphDestroy(batch->graph);
+  if (batch->exec) (void)hipGraphExecDestroy(batch->exec);
+  if (batch->graph) (void)hipGraphDestroy(batch->graph);
   delete batch;
 }
 

@@ -229,7 +229,7 @@ class Solver final : public ISolver {
 
   void set_graph_budget(int budget) override {
     if (budget > 0 && tm_id_ != KT_NONE) {
-      timer_flush();
+      if (timer_flush() != hipSuccess) tm_err_ = true;
       tm_id_ = KT_NONE;
     }
     graph_budget_ = budget;
@@ -412,10 +412,12 @@ class Solver final : public ISolver {
     tm_ms_ = 0.0;
     tm_launches_ = 0;
     tm_work_ = 0;
+    tm_err_ = false;
     return hipSuccess;
   }
   hipError_t timer_read(double* ms, long long* launches, double* work_bytes) override {
     TG_CHECK(timer_flush());
+    if (tm_err_) return hipErrorUnknown;
     *ms = tm_ms_;
     *launches = tm_launches_;
     *work_bytes = (double)tm_work_ * unit_bytes(tm_id_);
@@ -430,10 +432,14 @@ class Solver final : public ISolver {
       launch();
       return;
     }
-    if (tm_used_ == TM_CAP) timer_flush();
-    hipEventRecord(tm_ev_[2 * tm_used_], st_);
+    if (tm_used_ == TM_CAP && timer_flush() != hipSuccess) tm_err_ = true;
+    if (tm_used_ == TM_CAP) {  // the flush failed: launch untimed
+      launch();
+      return;
+    }
+    if (hipEventRecord(tm_ev_[2 * tm_used_], st_) != hipSuccess) tm_err_ = true;
     launch();
-    hipEventRecord(tm_ev_[2 * tm_used_ + 1], st_);
+    if (hipEventRecord(tm_ev_[2 * tm_used_ + 1], st_) != hipSuccess) tm_err_ = true;
     ++tm_used_;
     ++tm_launches_;
     tm_work_ += work;
@@ -647,10 +653,11 @@ class Solver final : public ISolver {
   double tm_ms_ = 0.0;
   long long tm_launches_ = 0;
   long long tm_work_ = 0;
+  bool tm_err_ = false;  // an event call failed since the timer was enabled
 
  public:
   ~Solver() override {
-    for (auto& e : tm_ev_) hipEventDestroy(e);
+    for (auto& e : tm_ev_) (void)hipEventDestroy(e);
   }
 };
 
