@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-equal-accuracy", action="store_true",
+                    help="skip the FP64 runs that match the FP32-mixed gradient accuracy")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--timer-kernel", default="z_matvec", choices=sorted(KERNEL_FIELDS))
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -74,8 +76,10 @@ def load_traffic(kernel, n, prec):
     return ent.get("bytes_per_launch")
 
 
-def run_precision(torch, api, inputs, pr, c_obs, precision, args, steps, warmup, timer):
-    plan = api.Plan(pr.n, pr.nt, pr.centres, pr.sigma, T=pr.T, rtol=args.rtol,
+def run_precision(torch, api, inputs, pr, c_obs, precision, args, steps, warmup, timer,
+                  rtol=None, keep_state=False):
+    plan = api.Plan(pr.n, pr.nt, pr.centres, pr.sigma, T=pr.T,
+                    rtol=args.rtol if rtol is None else rtol,
                     ckpt_stride=args.ckpt, precision=precision)
     dev = torch.device("cuda:0")
     dt = torch.float32 if precision == "fp32" else torch.float64
@@ -85,8 +89,10 @@ def run_precision(torch, api, inputs, pr, c_obs, precision, args, steps, warmup,
     kf = torch.tensor([pr.k_f], dtype=torch.float64, device=dev)
     d = c_obs.to(dt)
 
+    cT = []
+
     def step():
-        plan.forward(p, rho, kf, m)
+        cT[:] = [plan.forward(p, rho, kf, m)]
         s1 = plan.stats()
         J, gp, gr, gk = plan.adjoint_misfit(d)
         s2 = plan.stats()
@@ -123,12 +129,54 @@ def run_precision(torch, api, inputs, pr, c_obs, precision, args, steps, warmup,
         "worst_rel_residual": max(s1.worst_rel_residual, s2.worst_rel_residual),
         "gp": gp.detach().cpu().numpy(),
     }
+    if keep_state:
+        res["cT"] = cT[0].double().cpu().numpy()
     if tinfo:
         ms, launches, work_bytes = tinfo
         res["timer"] = {"kernel": timer, "ms": ms, "launches": launches,
                         "work_bytes": work_bytes}
     del plan
     torch.cuda.empty_cache()
+    return res
+
+
+def rel_errors(np, a, ref):
+    """Relative errors of a run's results against a reference run."""
+    out = {"J": abs(a["J"] - ref["J"]) / abs(ref["J"]),
+           "g_p": float(np.linalg.norm(a["gp"] - ref["gp"]) / np.linalg.norm(ref["gp"])),
+           "g_rho": abs(a["g_rho"] - ref["g_rho"]) / abs(ref["g_rho"]),
+           "g_kf": abs(a["g_kf"] - ref["g_kf"]) / abs(ref["g_kf"])}
+    if "cT" in a and "cT" in ref:
+        out["cT_rel_l2"] = float(np.linalg.norm(a["cT"] - ref["cT"]) / np.linalg.norm(ref["cT"]))
+    return out
+
+
+def equal_accuracy(torch, np, api, inputs, pr, c_obs, args, r32):
+    """FP32-mixed against FP64 at equal gradient accuracy.  Reference: the
+    FP64 path at rtol 1e-11 (itself within 1e-10 of the FP64 oracle).  The
+    FP64 path is then run at growing accuracy (rtol 1e-5 .. 1e-7) until its
+    g_p error is at most the FP32-mixed one; that run is timed again after a
+    warm-up and compared with the FP32-mixed time per gradient."""
+    ref = run_precision(torch, api, inputs, pr, c_obs, "fp64", args, 1, 0, None, rtol=1e-11,
+                        keep_state=True)
+    e32 = rel_errors(np, r32, ref)
+    ladder = []
+    chosen = None
+    for rt in (1e-5, 3e-6, 1e-6, 3e-7, 1e-7):
+        r = run_precision(torch, api, inputs, pr, c_obs, "fp64", args, 1, 0, None, rtol=rt)
+        e = rel_errors(np, r, ref)
+        ladder.append({"rtol": rt, "g_p": e["g_p"], "pcg_its": r["pcg_its_forward"] +
+                       r["pcg_its_adjoint"]})
+        if e["g_p"] <= e32["g_p"]:
+            chosen = (rt, e)
+            break
+    res = {"reference": "FP64 path at PCG rtol 1e-11", "fp32_mixed_err": e32,
+           "fp32_mixed_s": r32["ms_per_step"] / 1000.0, "fp64_ladder": ladder}
+    if chosen is not None:
+        rt, e = chosen
+        r = run_precision(torch, api, inputs, pr, c_obs, "fp64", args, 1, 1, None, rtol=rt)
+        res.update({"fp64_rtol": rt, "fp64_err": e, "fp64_s": r["ms_per_step"] / 1000.0,
+                    "speedup": r["ms_per_step"] / r32["ms_per_step"]})
     return res
 
 
@@ -281,7 +329,7 @@ def main():
         del a, b
 
     r32 = run_precision(torch, api, inputs, pr, c_obs, "fp32", args, args.steps, args.warmup,
-                        args.timer_kernel)
+                        args.timer_kernel, keep_state=not args.no_fp64)
     r64 = None
     if not args.no_fp64:
         r64 = run_precision(torch, api, inputs, pr, c_obs, "fp64", args, args.fp64_steps,
@@ -343,6 +391,9 @@ def main():
             },
             "pcg_its_forward": r64["pcg_its_forward"], "pcg_its_adjoint": r64["pcg_its_adjoint"],
         }
+        if not args.no_equal_accuracy:
+            out["fp64"]["equal_accuracy"] = equal_accuracy(torch, np, api, inputs, pr, c_obs,
+                                                           args, r32)
     if not args.no_batch:
         out["batch"] = batch_workload(torch, np, api, inputs, args.batch_reps)
     if not args.no_hvp:

@@ -152,10 +152,14 @@ tg_status tg_plan_get_schedule(const tg_plan* plan, int* pencils, int* z_waves, 
 /* Per-pass override of the schedule, applied after tg_plan_set_schedule
  * (which resets every pass to its plan-wide values).  kernel_id names one
  * pass of the PCG iteration as in tg_kernel_timer: 1, 2, 4, 5 (x/y passes:
- * pencils 8, 16 or 32) or 3 (z matvec: pencils 0).  waves_per_simd: 1 or 4
+ * pencils 8, 16 or 32) or 3 (z matvec: 0, 8 or 16, see below).  waves_per_simd: 1 or 4
  * as above.  Results are identical up to the summation order of the FP64
  * partial sums.  Errors: TG_ERR_ARG for an unknown pass or value (the plan
- * keeps its schedule), TG_ERR_WORKSPACE before tg_plan_bind. */
+ * keeps its schedule), TG_ERR_WORKSPACE before tg_plan_bind.  For the z
+ * matvec, pencils selects the layout of a spectral row in registers: 8 for
+ * one complex value per lane access, 16 for a pair (16-byte accesses in
+ * FP32), 0 for the default (16 in FP32, 8 in FP64); z_waves 8 allows
+ * neither. */
 tg_status tg_plan_set_pass(tg_plan* plan, int kernel_id, int pencils, int waves_per_simd);
 tg_status tg_plan_get_pass(const tg_plan* plan, int kernel_id, int* pencils,
                            int* waves_per_simd);

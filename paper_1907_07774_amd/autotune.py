@@ -113,7 +113,8 @@ def tune_passes(plan, p, rho_f, k_f, m, reps: int = 2, verbose: bool = False):
     chosen = {}
     for name in PASSES:
         if name == "z_matvec":
-            opts = [] if zw == 8 else [(0, o) for o in OCCUPANCY]
+            # row layout in registers: single complex values or pairs
+            opts = [] if zw == 8 else [(a, o) for a in (8, 16) for o in OCCUPANCY]
         else:
             opts = [(c, o) for c in PENCILS for o in OCCUPANCY]
         cur = best = plan.get_pass(name)

@@ -278,7 +278,9 @@ tg_status tg_plan_set_pass(tg_plan* plan, int kernel_id, int pencils, int waves_
   if (!plan->solver) return TG_ERR_WORKSPACE;
   if (kernel_id < tg::KT_X_INV_GRAD || kernel_id > tg::KT_LAST) return TG_ERR_ARG;
   const bool zpass = kernel_id == tg::KT_Z_MATVEC;
-  if (zpass ? pencils != 0 : !(pencils == 8 || pencils == 16 || pencils == 32)) return TG_ERR_ARG;
+  if (zpass ? !(pencils == 0 || pencils == 8 || pencils == 16)
+            : !(pencils == 8 || pencils == 16 || pencils == 32))
+    return TG_ERR_ARG;
   if (!(waves_per_simd == 1 || waves_per_simd == 4)) return TG_ERR_ARG;
   if (!plan->solver->set_pass(kernel_id, pencils, waves_per_simd)) return TG_ERR_ARG;
   return TG_OK;

@@ -508,6 +508,112 @@ __device__ __forceinline__ void r2c_row(cx<T> (&v)[E], cx<T>* lds, int t, int ro
   (void)L;
 }
 
+// ---- pair layout: register 2e + s holds complex position k = 2 q + s of
+// the row, q = t + TT e (e < E/2), so each lane moves whole 16-byte (FP32)
+// pairs to and from memory.  The real-transform pre/post-processing is the
+// same as above; the length-L transform is split into its even and odd
+// halves: the inverse is two half-length inverse transforms of the even
+// and odd positions (input in pair layout) combined with W_L^-n
+// (decimation in time), the forward combines x[n] and x[n + L/2] with
+// W_L^n first and ends with two half-length transforms whose outputs are
+// the even and odd positions (decimation in frequency).  Values in real
+// space keep the register mapping of the other helpers (position t + TT e).
+template <typename T>
+struct alignas(4 * sizeof(T)) cx2 {
+  cx<T> a, b;
+};
+
+// Mirror partner X[L - k] of every register in pair layout.  k = 2q + 1:
+// position 2 (K - 1 - q) + 1 = register 2 (E/2 - 1 - e) + 1 of lane
+// TT - 1 - t.  k = 2q: position 2 (K - q), register 2 (E/2 - 1 - e) of
+// lane TT - t for t >= 1, own register 2 ((E/2 - e) mod E/2) for t = 0.
+template <typename T, int TT, int E>
+__device__ __forceinline__ void mirror_pairs(const cx<T> (&v)[E], cx<T> (&m)[E], int t) {
+  constexpr int E2 = E / 2;
+#pragma unroll
+  for (int e = 0; e < E2; ++e) {
+    const cx<T> own0 = v[2 * ((E2 - e) % E2)];
+    if constexpr (TT == 1) {
+      m[2 * e] = own0;
+      m[2 * e + 1] = v[2 * (E2 - 1 - e) + 1];
+    } else {
+      const cx<T> other0 = shfl_cx(v[2 * (E2 - 1 - e)], (TT - t) & (TT - 1), TT);
+      m[2 * e] = (t == 0) ? own0 : other0;
+      m[2 * e + 1] = shfl_cx(v[2 * (E2 - 1 - e) + 1], TT - 1 - t, TT);
+    }
+  }
+}
+
+// C2R as c2r_row, input in pair layout, output in the usual mapping.
+template <typename T, int N, int E>
+__device__ __forceinline__ void c2r_pairs(cx<T> (&v)[E], cx<T>* lds, int t, int row) {
+  using Z = ZP<T, N, ZDefaultRows<N>::value, E>;
+  constexpr int L = Z::L, TT = Z::TT, E2 = E / 2, K = L / 2;
+  static_assert(E % 2 == 0 && Z::PITCH >= K + K / E2, "pair layout");
+  cx<T> mr[E];
+  mirror_pairs<T, TT, E>(v, mr, t);
+  cx<T> a[E2], b[E2];
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int k = 2 * (t + TT * (i / 2)) + (i & 1);
+    const cx<T> xk = v[i];
+    cx<T> z;
+    if (k == 0) {
+      z = mk(xk.x + xk.y, xk.x - xk.y);
+    } else {
+      const cx<T> xm = conjg(mr[i]);
+      const cx<T> sum = xk + xm, dif = xk - xm;
+      const cx<T> tdif = cmul(conjg(twiddle<T, false, N>(k)), dif);
+      z = sum + mk(-tdif.y, tdif.x);
+    }
+    if (i & 1) b[i / 2] = z; else a[i / 2] = z;
+  }
+  fft<T, K, E2, true, 1, Z::PITCH, true, true>(a, lds, t, row);
+  fft<T, K, E2, true, 1, Z::PITCH, true, true>(b, lds, t, row);
+#pragma unroll
+  for (int e = 0; e < E2; ++e) {
+    const cx<T> u = cmul(conjg(twiddle<T, false, L>(t + TT * e)), b[e]);
+    v[e] = a[e] + u;
+    v[e + E2] = a[e] - u;
+  }
+}
+
+// R2C as r2c_row, input in the usual mapping, output in pair layout.
+template <typename T, int N, int E>
+__device__ __forceinline__ void r2c_pairs(cx<T> (&v)[E], cx<T>* lds, int t, int row) {
+  using Z = ZP<T, N, ZDefaultRows<N>::value, E>;
+  constexpr int L = Z::L, TT = Z::TT, E2 = E / 2, K = L / 2;
+  cx<T> a[E2], b[E2];
+#pragma unroll
+  for (int e = 0; e < E2; ++e) {
+    const cx<T> x0 = v[e], x1 = v[e + E2];
+    a[e] = x0 + x1;
+    b[e] = cmul(twiddle<T, false, L>(t + TT * e), x0 - x1);
+  }
+  fft<T, K, E2, false, 1, Z::PITCH, true, true>(a, lds, t, row);
+  fft<T, K, E2, false, 1, Z::PITCH, true, true>(b, lds, t, row);
+#pragma unroll
+  for (int e = 0; e < E2; ++e) {
+    v[2 * e] = a[e];
+    v[2 * e + 1] = b[e];
+  }
+  cx<T> mr[E];
+  mirror_pairs<T, TT, E>(v, mr, t);
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int k = 2 * (t + TT * (i / 2)) + (i & 1);
+    const cx<T> zk = v[i];
+    if (k == 0) {
+      v[i] = mk(zk.x + zk.y, zk.x - zk.y);
+    } else {
+      const cx<T> zm = conjg(mr[i]);
+      const cx<T> sum = zk + zm, dif = zk - zm;
+      const cx<T> td = cmul(twiddle<T, false, N>(k), dif);
+      v[i] = scale(sum + mk(td.y, -td.x), T(0.5));
+    }
+  }
+}
+
 #define ZP_SETUP                                                        \
   using Z = ZP<T, N, RW>;                                               \
   constexpr int E = Z::E, TT = Z::TT;                                   \
@@ -530,7 +636,7 @@ __device__ __forceinline__ void r2c_row(cx<T> (&v)[E], cx<T>* lds, int t, int ro
 // products, then FP64): with |u|^2 this gives <u, A u> of the Crank-Nicolson
 // operator, because the spectral divergence is minus the adjoint of the
 // spectral gradient.
-template <typename T, int N, int RW, int PRE_, int OCC, int EZ>
+template <typename T, int N, int RW, int PRE_, int OCC, int EZ, bool PAIR>
 __global__ void TG_BOUNDS((ZP<T, N, RW, EZ>::NT), OCC)
 k_z_matvec(cx<T>* __restrict__ V1, cx<T>* __restrict__ V2, cx<T>* __restrict__ V3,
            const T* __restrict__ m, long long m_bs, const ProbScalars* __restrict__ sc,
@@ -548,6 +654,25 @@ k_z_matvec(cx<T>* __restrict__ V1, cx<T>* __restrict__ V2, cx<T>* __restrict__ V
   const long long sbase = (long long)b * Z::SPEC + grow * Z::L;
   const cx<T>* mrow = reinterpret_cast<const cx<T>*>(m + b * m_bs + grow * N);
   cx<T>* Vs[3] = {V1 + sbase, V2 + sbase, V3 + sbase};
+  // spectral row in and out: position t + TT e, or pairs 2q, 2q + 1 with
+  // q = t + TT e in pair layout (one 16-byte access per pair in FP32)
+  auto load_row = [&](int j, cx<T>(&u)[E]) {
+    if constexpr (PAIR) {
+      const cx2<T>* r2 = reinterpret_cast<const cx2<T>*>(Vs[j]);
+#pragma unroll
+      for (int e = 0; e < E / 2; ++e) {
+        const cx2<T> w = r2[t + TT * e];
+        u[2 * e] = w.a;
+        u[2 * e + 1] = w.b;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) u[e] = Vs[j][t + TT * e];
+    }
+  };
+  auto pos = [&](int i) {  // spectral position held in register i
+    return PAIR ? 2 * (t + TT * (i / 2)) + (i & 1) : t + TT * i;
+  };
   constexpr int PRE = PRE_;  // rows held in registers at once (1 or 3)
   // PRE = 3 keeps m in registers for all three rows; PRE = 1 re-reads the
   // m row (a cache hit after the first row) to save registers.
@@ -558,21 +683,17 @@ k_z_matvec(cx<T>* __restrict__ V1, cx<T>* __restrict__ V2, cx<T>* __restrict__ V
     for (int e = 0; e < E; ++e) mv[e] = mrow[t + TT * e];
   }
 #pragma unroll
-  for (int j = 0; j < PRE; ++j)
-#pragma unroll
-    for (int e = 0; e < E; ++e) v[j][e] = Vs[j][t + TT * e];
+  for (int j = 0; j < PRE; ++j) load_row(j, v[j]);
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
     cx<T>(&u)[E] = v[PRE == 3 ? j : 0];
-    if (PRE == 1 && j > 0) {
-#pragma unroll
-      for (int e = 0; e < E; ++e) u[e] = Vs[j][t + TT * e];
-    }
+    if (PRE == 1 && j > 0) load_row(j, u);
     if (j == 2) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) u[e] = mul_i(u[e], (T)(t + TT * e));
+      for (int e = 0; e < E; ++e) u[e] = mul_i(u[e], (T)pos(e));
     }
-    c2r_row<T, N>(u, lds, t, row);
+    if constexpr (PAIR) c2r_pairs<T, N>(u, lds, t, row);
+    else c2r_row<T, N>(u, lds, t, row);
     T sj = T(0);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -585,11 +706,24 @@ k_z_matvec(cx<T>* __restrict__ V1, cx<T>* __restrict__ V2, cx<T>* __restrict__ V
     // pin the sum here: left alone, the compiler sinks it to its use at the
     // end of the kernel and keeps its inputs live through all three rows
     asm volatile("" : "+v"(mg));
-    r2c_row<T, N>(u, lds, t, row);
+    if constexpr (PAIR) r2c_pairs<T, N>(u, lds, t, row);
+    else r2c_row<T, N>(u, lds, t, row);
+    if (j == 2) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      if (j == 2) u[e] = mul_i(u[e], (T)(t + TT * e));
-      Vs[j][t + TT * e] = u[e];
+      for (int e = 0; e < E; ++e) u[e] = mul_i(u[e], (T)pos(e));
+    }
+    if constexpr (PAIR) {
+      cx2<T>* r2 = reinterpret_cast<cx2<T>*>(Vs[j]);
+#pragma unroll
+      for (int e = 0; e < E / 2; ++e) {
+        cx2<T> w;
+        w.a = u[2 * e];
+        w.b = u[2 * e + 1];
+        r2[t + TT * e] = w;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) Vs[j][t + TT * e] = u[e];
     }
   }
   double acc[NSLOT] = {mg, 0.0, 0.0, 0.0};

@@ -120,9 +120,10 @@ struct SLaunch {
 };
 
 // z-pass launches.  The matvec kernel takes RW rows per workgroup and EZ
-// complex values per lane (L/EZ lanes per row); the time-step kernels use
-// the default lanes per row.
-template <typename T, int N, int RW, int OCC, int EZ = FftE<N / 2>::value>
+// complex values per lane (L/EZ lanes per row), in single or pair layout
+// (PAIR: 16-byte accesses in FP32); the time-step kernels use the default
+// lanes per row.
+template <typename T, int N, int RW, int OCC, int EZ = FftE<N / 2>::value, bool PAIR = false>
 struct ZLaunch {
   using Z = ZP<T, N, RW>;
   using ZM = ZP<T, N, RW * EZ / FftE<N / 2>::value, EZ>;  // same threads, EZ per lane
@@ -134,7 +135,7 @@ struct ZLaunch {
     // FP32 holds all three rows unless an occupancy floor asks for fewer
     // registers; FP64 always streams them one at a time.
     constexpr int PRE = (sizeof(T) == 4 && OCC < 4) ? 3 : 1;
-    k_z_matvec<T, N, ZM::RW, PRE, OCC, EZ><<<dim3(nbk, nb), ZM::NT, 0, st>>>(
+    k_z_matvec<T, N, ZM::RW, PRE, OCC, EZ, PAIR><<<dim3(nbk, nb), ZM::NT, 0, st>>>(
         V1, V2, V3, m, m_bs, sc, part, pred, rev, k * nbk);
   }
   template <int MODE>
@@ -194,26 +195,32 @@ bool set_strided(Sched<T, N>& s, int C, int occ, int pass = -1) {
   return false;
 }
 
-// matvec_only: replace only the z matvec kernel (its occupancy floor)
+// Rows per z workgroup: one, two or four waves.  matvec_only: replace only
+// the z matvec kernel (its occupancy floor and access layout).
+template <typename T, int N, int RW, int OCC>
+void fill_z(Sched<T, N>& s, bool matvec_only, bool pair) {
+  if (!matvec_only) ZLaunch<T, N, RW, OCC>::fill(s);
+  if (pair) ZLaunch<T, N, RW, OCC, FftE<N / 2>::value, true>::fill_matvec(s);
+  else ZLaunch<T, N, RW, OCC>::fill_matvec(s);
+}
+
 template <typename T, int N, int OCC>
-bool set_zrows_occ(Sched<T, N>& s, int waves, bool matvec_only) {
+bool set_zrows_occ(Sched<T, N>& s, int waves, bool matvec_only, bool pair) {
   constexpr int TT = ZP<T, N>::TT;
   constexpr int r1 = 64 / TT;
   switch (waves) {
     case 1:
-      if (matvec_only) ZLaunch<T, N, r1, OCC>::fill_matvec(s); else ZLaunch<T, N, r1, OCC>::fill(s);
+      fill_z<T, N, r1, OCC>(s, matvec_only, pair);
       return true;
     case 2:
       if constexpr (N * N >= 2 * r1) {
-        if (matvec_only) ZLaunch<T, N, 2 * r1, OCC>::fill_matvec(s);
-        else ZLaunch<T, N, 2 * r1, OCC>::fill(s);
+        fill_z<T, N, 2 * r1, OCC>(s, matvec_only, pair);
         return true;
       }
       return false;
     case 4:
       if constexpr (N * N >= 4 * r1) {
-        if (matvec_only) ZLaunch<T, N, 4 * r1, OCC>::fill_matvec(s);
-        else ZLaunch<T, N, 4 * r1, OCC>::fill(s);
+        fill_z<T, N, 4 * r1, OCC>(s, matvec_only, pair);
         return true;
       }
       return false;
@@ -222,9 +229,9 @@ bool set_zrows_occ(Sched<T, N>& s, int waves, bool matvec_only) {
 }
 
 template <typename T, int N>
-bool set_zrows(Sched<T, N>& s, int waves, int occ, bool matvec_only = false) {
-  if (occ == 4) return set_zrows_occ<T, N, 4>(s, waves, matvec_only);
-  if (occ == 1) return set_zrows_occ<T, N, 1>(s, waves, matvec_only);
+bool set_zrows(Sched<T, N>& s, int waves, int occ, bool matvec_only = false, bool pair = false) {
+  if (occ == 4) return set_zrows_occ<T, N, 4>(s, waves, matvec_only, pair);
+  if (occ == 1) return set_zrows_occ<T, N, 1>(s, waves, matvec_only, pair);
   return false;
 }
 

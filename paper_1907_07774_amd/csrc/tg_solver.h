@@ -72,8 +72,9 @@ class Solver final : public ISolver {
     // zwaves 8: one-wave z workgroups whose matvec kernel uses twice the
     // lanes per row (see set_zmatvec_wide)
     const bool wide = zwaves == 8;
-    if (!set_zrows<T, N>(s, wide ? 1 : zwaves, occ)) {
-      if (!set_zrows<T, N>(s, 1, occ)) return false;
+    const bool pair = !wide && kZPairDefault;
+    if (!set_zrows<T, N>(s, wide ? 1 : zwaves, occ, false, pair)) {
+      if (!set_zrows<T, N>(s, 1, occ, false, pair)) return false;
       zwaves = 1;
     }
     if (wide && !set_zmatvec_wide<T, N>(s, occ)) return false;
@@ -83,7 +84,7 @@ class Solver final : public ISolver {
     nslab_ = slabs;
     occ_ = occ;
     for (int id = 1; id <= KT_LAST; ++id) {
-      pass_C_[id] = id == KT_Z_MATVEC ? 0 : C;
+      pass_C_[id] = id == KT_Z_MATVEC ? (wide ? 8 : (pair ? 16 : 8)) : C;
       pass_occ_[id] = occ;
     }
     return true;
@@ -94,14 +95,17 @@ class Solver final : public ISolver {
     *slabs = nslab_;
     *occ = occ_;
   }
-  // Tile shape of one PCG pass (KT_* id): pencils for the x/y passes (0
-  // for the z matvec) and its occupancy floor.
+  // Tile shape of one PCG pass (KT_* id): pencils for the x/y passes; for
+  // the z matvec the bytes per lane access of a spectral row (8: one
+  // complex value, 16: a pair of them, 0: the default) and its occupancy
+  // floor.
   bool set_pass(int id, int C, int occ) override {
     if (id < 1 || id > KT_LAST) return false;
     Sched<T, N> s = sch_;
     if (id == KT_Z_MATVEC) {
-      if (C != 0 || zwaves_ == 8) return false;
-      if (!set_zrows<T, N>(s, zwaves_, occ, true)) return false;
+      if (C == 0) C = kZPairDefault ? 16 : 8;
+      if ((C != 8 && C != 16) || zwaves_ == 8) return false;
+      if (!set_zrows<T, N>(s, zwaves_, occ, true, C == 16)) return false;
     } else {
       if (!set_strided<T, N>(s, C, occ, id)) return false;
     }
@@ -639,6 +643,10 @@ class Solver final : public ISolver {
   int nslab_ = 1;
   int occ_ = 1;
   int pass_C_[KT_LAST + 1] = {};
+  // default layout of the z matvec's spectral rows: pairs in FP32 (16-byte
+  // accesses; measured 92 against 99 us per launch at 256^3), single
+  // complex values (already 16 bytes) in FP64
+  static constexpr bool kZPairDefault = sizeof(T) == 4;
   int pass_occ_[KT_LAST + 1] = {};
   static bool slabs_fit(const Sched<T, N>& s, int slabs) {
     return s.yi_nblk % slabs == 0 && s.yf_nblk % slabs == 0 && s.zm_nblk % slabs == 0 &&

@@ -14,9 +14,9 @@ pytestmark = pytest.mark.gpu
 
 PLAN_WIDE = [(8, 1, 1, 1), (32, 2, 2, 4), (16, 4, 4, 1), (16, 8, 1, 4), (32, 1, 8, 1)]
 PER_PASS = [
-    ((16, 1, 2, 1), {"x_inv_grad": (8, 4), "y_inv_grad": (32, 1), "z_matvec": (0, 4),
+    ((16, 1, 2, 1), {"x_inv_grad": (8, 4), "y_inv_grad": (32, 1), "z_matvec": (8, 4),
                      "y_fwd_div": (16, 4), "x_fwd_div": (32, 1)}),
-    ((32, 2, 1, 4), {"x_inv_grad": (32, 4), "y_inv_grad": (8, 1), "z_matvec": (0, 1),
+    ((32, 2, 1, 4), {"x_inv_grad": (32, 4), "y_inv_grad": (8, 1), "z_matvec": (16, 1),
                      "y_fwd_div": (32, 1), "x_fwd_div": (16, 1)}),
 ]
 
@@ -108,7 +108,7 @@ def test_schedule_errors():
     print("case schedule errors", flush=True)
     pr, p = problem(32)
     plan = api.Plan(32, pr.nt, pr.centres, pr.sigma, precision="fp64", schedule=(16, 1, 1, 1))
-    for bad in [("z_matvec", 16, 1), ("x_inv_grad", 12, 1), ("x_fwd_div", 16, 2),
+    for bad in [("z_matvec", 32, 1), ("x_inv_grad", 12, 1), ("x_fwd_div", 16, 2),
                 ("y_fwd_div", 0, 1)]:
         with pytest.raises(_lib.TumorGradError) as e:
             plan.set_pass(*bad)
@@ -119,7 +119,11 @@ def test_schedule_errors():
     assert plan.get_pass("x_inv_grad") == (16, 1)
     plan.set_pass("x_inv_grad", 8, 4)
     assert plan.get_pass("x_inv_grad") == (8, 4)
+    assert plan.get_pass("z_matvec") == (8, 1)  # FP64 default: one complex per access
+    plan.set_pass("z_matvec", 8, 4)
+    assert plan.get_pass("z_matvec") == (8, 4)
     plan.set_schedule(32, 8, 1, 1)  # resets every pass
     assert plan.get_pass("x_inv_grad") == (32, 1)
+    assert plan.get_pass("z_matvec") == (8, 1)
     with pytest.raises(_lib.TumorGradError):
         plan.set_pass("z_matvec", 0, 4)  # the wide z matvec has no per-pass variant
