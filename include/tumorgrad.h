@@ -187,9 +187,10 @@ tg_status tg_kernel_timer_read(tg_plan* plan, double* total_ms, long long* launc
  * (tg_forward then tg_adjoint_misfit) on that plan's batch of problems, all
  * captured on `stream` into one graph.  Inside the graph every PCG solve
  * runs a fixed, predicated iteration budget (kernels of converged problems
- * return at once): pcg_budget, or if 0 the plan's largest per-solve count
- * of its last eager forward/gradient + 25% + 4 (TG_ERR_STATE if there was
- * none).  A solve that needs more is flagged TG_ERR_NOT_CONVERGED in
+ * return at once): pcg_budget for every solve, or if 0 each solve's own
+ * iteration count in the plan's last eager tg_forward / tg_adjoint_misfit
+ * + 25% + 4 (the solves of a call come in a fixed order; TG_ERR_STATE if
+ * there was no eager call).  A solve that needs more is flagged TG_ERR_NOT_CONVERGED in
  * tg_stats after the launch.  The io pointers are baked into the graph and
  * must stay valid; their contents may change between launches. */
 typedef struct tg_batch tg_batch;

@@ -328,11 +328,11 @@ tg_status tg_batch_capture(int nplans, tg_plan* const* plans, const tg_batch_io*
   for (int i = 0; i < nplans && e == hipSuccess; ++i) {
     tg_plan* p = plans[i];
     const tg_batch_io& b = io[i];
-    p->solver->set_graph_budget(budgets[i]);
+    p->solver->set_graph_budget(budgets[i], pcg_budget == 0);
     e = p->solver->forward(b.d_p, b.d_rho_f, b.d_k_f, b.d_m, b.d_cT, st);
     if (e == hipSuccess)
       e = p->solver->vjp(nullptr, b.d_cobs, b.d_J, b.d_gp, b.d_grho, b.d_gkf, st);
-    p->solver->set_graph_budget(0);
+    p->solver->set_graph_budget(0, false);
     p->last_stream = st;
   }
   hipGraph_t graph = nullptr;

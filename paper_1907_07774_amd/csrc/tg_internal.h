@@ -88,9 +88,11 @@ class ISolver {
   // and an occupancy floor for the PCG pass kernels (1: none, 4: >= 4 waves
   // per SIMD); 0 = default.  False if not available.
   virtual bool set_schedule(int C, int zwaves, int slabs, int occ) = 0;
-  // Graph-capture mode: every PCG solve runs exactly `budget` predicated
-  // iterations with no host synchronization (0 = eager, adaptive).
-  virtual void set_graph_budget(int budget) = 0;
+  // Graph-capture mode: every PCG solve runs a fixed number of predicated
+  // iterations with no host synchronization: `budget`, or with per_solve
+  // the solve's count in the last eager call of the same kind + 25% + 4
+  // (at most `budget`) (budget 0 = eager, adaptive).
+  virtual void set_graph_budget(int budget, bool per_solve) = 0;
   // Largest PCG iteration count of one solve seen since the last forward.
   virtual int its_max_last_call() const = 0;
   virtual void get_schedule(int* C, int* zwaves, int* slabs, int* occ) const = 0;

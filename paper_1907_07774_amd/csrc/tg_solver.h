@@ -128,6 +128,7 @@ class Solver final : public ISolver {
     st_ = st;
     call_status_ = 0;
     its_max_call_ = 0;
+    begin_call(0);
     m_ = (const T*)m;
     cT_ = (T*)cT;
     Ctx c = prim();
@@ -149,6 +150,7 @@ class Solver final : public ISolver {
     TG_LAUNCH_CHECK();
     TG_CHECK(fwd_steps(c, 0, d_.nt, /*initial=*/true));
     live_seg_ = d_.nseg - 1;
+    end_call();
     return hipSuccess;
   }
 
@@ -157,6 +159,7 @@ class Solver final : public ISolver {
                  double* gkf, hipStream_t st) override {
     st_ = st;
     call_status_ = 0;
+    begin_call(1);
     Ctx c = prim();
     stat_sc_ = c.sc;
     stat_nb_ = c.nb;
@@ -176,6 +179,7 @@ class Solver final : public ISolver {
     k_emit_grads<<<(d_.batch + 63) / 64, 64, 0, st_>>>(w_.sc, cobs ? J : nullptr, grho, gkf,
                                                        d_.batch);
     TG_LAUNCH_CHECK();
+    end_call();
     return hipSuccess;
   }
 
@@ -183,6 +187,7 @@ class Solver final : public ISolver {
   hipError_t hessvec(int ndir, const double* V, double* HV, hipStream_t st) override {
     st_ = st;
     call_status_ = 0;
+    begin_call(2);
     Ctx dc = dirs(ndir);
     stat_sc_ = dc.sc;
     stat_nb_ = ndir;
@@ -231,12 +236,13 @@ class Solver final : public ISolver {
 
   int last_status() const override { return call_status_; }
 
-  void set_graph_budget(int budget) override {
+  void set_graph_budget(int budget, bool per_solve) override {
     if (budget > 0 && tm_id_ != KT_NONE) {
       if (timer_flush() != hipSuccess) tm_err_ = true;
       tm_id_ = KT_NONE;
     }
     graph_budget_ = budget;
+    graph_per_solve_ = per_solve;
   }
   int its_max_last_call() const override { return its_max_call_; }
 
@@ -360,7 +366,19 @@ class Solver final : public ISolver {
   // In graph mode the iteration budget is the iteration cap, so a solve
   // that needs more is flagged NOT_CONVERGED instead of silently stopping.
   int maxit() const {
-    return graph_budget_ > 0 ? std::min(graph_budget_, d_.maxit) : d_.maxit;
+    return graph_budget_ > 0 ? std::min(cur_budget_, d_.maxit) : d_.maxit;
+  }
+
+  // Per-solve iteration counts of the last eager call of each kind
+  // (0 forward, 1 vjp, 2 hessvec): the solves of a call come in a fixed
+  // order, so a graph captured later can give each one its own budget.
+  void begin_call(int kind) {
+    kind_ = kind;
+    seq_ = 0;
+    rec_.clear();
+  }
+  void end_call() {
+    if (graph_budget_ == 0) hist_[kind_] = rec_;
   }
 
   double rtol() const {
@@ -464,8 +482,15 @@ class Solver final : public ISolver {
   // done flags between chunks.
   hipError_t pcg_loop(const Ctx& c) {
     if (graph_budget_ > 0) {
-      // graph capture: a fixed, predicated iteration budget, no host reads
-      for (int i = 0; i < graph_budget_; ++i) pcg_iteration(c);
+      // graph capture: a fixed, predicated iteration budget, no host reads;
+      // per solve (its last eager count + 25% + 4) when known
+      int budget = graph_budget_;
+      const std::vector<int>& h = hist_[kind_];
+      if (graph_per_solve_ && seq_ < h.size())
+        budget = std::min(graph_budget_, h[seq_] + h[seq_] / 4 + 4);
+      ++seq_;
+      cur_budget_ = budget;
+      for (int i = 0; i < budget; ++i) pcg_iteration(c);
       return hipGetLastError();
     }
     int launched = 0;
@@ -490,6 +515,8 @@ class Solver final : public ISolver {
     }
     its_est_ = std::max(1, maxseen);
     its_max_call_ = std::max(its_max_call_, maxseen);
+    rec_.push_back(maxseen);
+    ++seq_;
     if (tm_id_ != KT_NONE) {
       long long eff = 0;
       for (int b = 0; b < c.nb; ++b) eff += hsc_[b].its;
@@ -636,6 +663,12 @@ class Solver final : public ISolver {
   int live_seg_ = -1;
   int call_status_ = 0;
   int graph_budget_ = 0;
+  bool graph_per_solve_ = false;
+  int cur_budget_ = 0;
+  std::vector<int> hist_[3];
+  std::vector<int> rec_;
+  int kind_ = 0;
+  size_t seq_ = 0;
   double fp32_floor_ = 0.0;
   int its_max_call_ = 0;
   Sched<T, N> sch_;
