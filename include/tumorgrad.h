@@ -137,13 +137,15 @@ tg_status tg_hessvec_gn(tg_plan* plan, int ndir, const double* d_V, double* d_HV
 
 /* Launch schedule of the transform passes (performance knobs only; results
  * are identical up to the summation order of the FP64 partial sums).
- * pencils: 8, 16 or 32 pencils per x/y-pass workgroup; z_waves: 1, 2 or 4
- * waves per z-pass workgroup, or 8 for one-wave workgroups whose matvec
- * z pass spreads each row over twice the default lanes; slabs: 1, 2, 4 or 8 x-plane slabs over which
- * the y-z-y pass chain of the diffusion operator runs slab by slab;
- * waves_per_simd: occupancy floor of the PCG pass kernels (1: registers
- * uncapped, 4: capped so four waves fit per SIMD); 0 selects the default.
- * Requires a bound plan.  Errors: TG_ERR_ARG for unsupported values. */
+ * pencils: 8, 16, 32 or 64 pencils per x/y-pass workgroup (64 only where
+ * its transform buffer fits the 160 KB of LDS: not FP64 at n = 256);
+ * z_waves: 1, 2 or 4 waves per z-pass workgroup, or 8 for one-wave
+ * workgroups whose matvec z pass spreads each row over twice the default
+ * lanes; slabs: 1, 2, 4 or 8 x-plane slabs over which the y-z-y pass chain
+ * of the diffusion operator runs slab by slab; waves_per_simd: occupancy
+ * floor of the PCG pass kernels (1: registers uncapped, 4: capped so four
+ * waves fit per SIMD); 0 selects the default.  Requires a bound plan.
+ * Errors: TG_ERR_ARG for unsupported values. */
 tg_status tg_plan_set_schedule(tg_plan* plan, int pencils, int z_waves, int slabs,
                                int waves_per_simd);
 tg_status tg_plan_get_schedule(const tg_plan* plan, int* pencils, int* z_waves, int* slabs,
@@ -152,14 +154,14 @@ tg_status tg_plan_get_schedule(const tg_plan* plan, int* pencils, int* z_waves, 
 /* Per-pass override of the schedule, applied after tg_plan_set_schedule
  * (which resets every pass to its plan-wide values).  kernel_id names one
  * pass of the PCG iteration as in tg_kernel_timer: 1, 2, 4, 5 (x/y passes:
- * pencils 8, 16 or 32) or 3 (z matvec: 0, 8 or 16, see below).  waves_per_simd: 1 or 4
- * as above.  Results are identical up to the summation order of the FP64
- * partial sums.  Errors: TG_ERR_ARG for an unknown pass or value (the plan
- * keeps its schedule), TG_ERR_WORKSPACE before tg_plan_bind.  For the z
- * matvec, pencils selects the layout of a spectral row in registers: 8 for
- * one complex value per lane access, 16 for a pair (16-byte accesses in
- * FP32), 0 for the default (16 in FP32, 8 in FP64); z_waves 8 allows
- * neither. */
+ * pencils as above) or 3 (z matvec: see below); waves_per_simd: 1 or 4 as
+ * above.  For the z matvec, pencils selects the layout of a spectral row in
+ * registers: 8 for one complex value per lane access, 16 for a pair
+ * (16-byte accesses in FP32), 0 for the default (16 in FP32, 8 in FP64);
+ * z_waves 8 allows neither.  Results are identical up to the summation
+ * order of the FP64 partial sums.  Errors: TG_ERR_ARG for an unknown pass
+ * or value (the plan keeps its schedule), TG_ERR_WORKSPACE before
+ * tg_plan_bind. */
 tg_status tg_plan_set_pass(tg_plan* plan, int kernel_id, int pencils, int waves_per_simd);
 tg_status tg_plan_get_pass(const tg_plan* plan, int kernel_id, int* pencils,
                            int* waves_per_simd);

@@ -1,6 +1,6 @@
 """Autotuner for the transform tile shapes.
 
-Plan-wide knobs: pencils per x/y workgroup (8, 16, 32), waves of rows per
+Plan-wide knobs: pencils per x/y workgroup (8, 16, 32, 64), waves of rows per
 z workgroup (1, 2, 4; 8 = one-wave workgroups with twice the lanes per row
 in the z matvec), x slabs of the y-z-y chain (1, 2, 4, 8) and an occupancy
 floor (1 or 4 waves per SIMD).  ``tune`` times one forward solve of a plan
@@ -17,7 +17,7 @@ import os
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(PKG, "schedules.json")
-PENCILS = (8, 16, 32)
+PENCILS = (8, 16, 32, 64)
 Z_WAVES = (1, 2, 4, 8)
 SLABS = (1, 2, 4, 8)
 OCCUPANCY = (1, 4)

@@ -254,7 +254,8 @@ tg_status tg_plan_set_schedule(tg_plan* plan, int pencils, int z_waves, int slab
                                int waves_per_simd) {
   if (plan == nullptr) return TG_ERR_ARG;
   if (!plan->solver) return TG_ERR_WORKSPACE;
-  if (!(pencils == 0 || pencils == 8 || pencils == 16 || pencils == 32)) return TG_ERR_ARG;
+  if (!(pencils == 0 || pencils == 8 || pencils == 16 || pencils == 32 || pencils == 64))
+    return TG_ERR_ARG;
   if (!(z_waves == 0 || z_waves == 1 || z_waves == 2 || z_waves == 4 || z_waves == 8))
     return TG_ERR_ARG;
   if (!(slabs == 0 || slabs == 1 || slabs == 2 || slabs == 4 || slabs == 8)) return TG_ERR_ARG;
@@ -279,7 +280,7 @@ tg_status tg_plan_set_pass(tg_plan* plan, int kernel_id, int pencils, int waves_
   if (kernel_id < tg::KT_X_INV_GRAD || kernel_id > tg::KT_LAST) return TG_ERR_ARG;
   const bool zpass = kernel_id == tg::KT_Z_MATVEC;
   if (zpass ? !(pencils == 0 || pencils == 8 || pencils == 16)
-            : !(pencils == 8 || pencils == 16 || pencils == 32))
+            : !(pencils == 8 || pencils == 16 || pencils == 32 || pencils == 64))
     return TG_ERR_ARG;
   if (!(waves_per_simd == 1 || waves_per_simd == 4)) return TG_ERR_ARG;
   if (!plan->solver->set_pass(kernel_id, pencils, waves_per_simd)) return TG_ERR_ARG;

@@ -168,8 +168,8 @@ struct ZLaunch {
   }
 };
 
-// Candidate tile shapes.  Pencils per x/y workgroup: 8, 16, 32 (row
-// segments of 64..512 bytes).  Rows per z workgroup: one, two or four waves.
+// Candidate tile shapes.  Pencils per x/y workgroup: 8, 16, 32, 64 (row
+// segments of 64..512 bytes in FP32).  Rows per z workgroup: one, two or four waves.
 // pass < 0: every x/y kernel; else one PCG pass (KT_* id).
 template <typename T, int N, int OCC>
 bool set_strided_occ(Sched<T, N>& s, int C, int pass) {
@@ -183,6 +183,15 @@ bool set_strided_occ(Sched<T, N>& s, int C, int pass) {
     case 32:
       if (pass < 0) SLaunch<T, N, 32, OCC>::fill(s); else SLaunch<T, N, 32, OCC>::fill_pass(s, pass);
       return true;
+    case 64:
+      // 64 pencils: 512-byte row segments; only where the workgroup's
+      // transform buffer and twiddle table fit the 160 KB of LDS
+      if constexpr ((long long)N * 64 * sizeof(cx<T>) + TW_LDS * sizeof(cx<T>) + 1024 <= 160 * 1024 &&
+                    64 * SP<T, N, 64, 0>::TT <= 1024) {
+        if (pass < 0) SLaunch<T, N, 64, OCC>::fill(s); else SLaunch<T, N, 64, OCC>::fill_pass(s, pass);
+        return true;
+      }
+      return false;
   }
   return false;
 }

@@ -12,12 +12,13 @@ from paper_1907_07774_amd import _lib, api, inputs
 
 pytestmark = pytest.mark.gpu
 
-PLAN_WIDE = [(8, 1, 1, 1), (32, 2, 2, 4), (16, 4, 4, 1), (16, 8, 1, 4), (32, 1, 8, 1)]
+PLAN_WIDE = [(8, 1, 1, 1), (32, 2, 2, 4), (16, 4, 4, 1), (16, 8, 1, 4), (32, 1, 8, 1),
+             (64, 2, 1, 1)]
 PER_PASS = [
     ((16, 1, 2, 1), {"x_inv_grad": (8, 4), "y_inv_grad": (32, 1), "z_matvec": (8, 4),
                      "y_fwd_div": (16, 4), "x_fwd_div": (32, 1)}),
     ((32, 2, 1, 4), {"x_inv_grad": (32, 4), "y_inv_grad": (8, 1), "z_matvec": (16, 1),
-                     "y_fwd_div": (32, 1), "x_fwd_div": (16, 1)}),
+                     "y_fwd_div": (64, 1), "x_fwd_div": (64, 4)}),
 ]
 
 
