@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-fixed", action="store_true",
+                    help="skip the (rho_f, k_f) = (10, 0.1) leg")
     ap.add_argument("--no-equal-accuracy", action="store_true",
                     help="skip the FP64 runs that match the FP32-mixed gradient accuracy")
     ap.add_argument("--no-cpu", action="store_true")
@@ -77,7 +79,7 @@ def load_traffic(kernel, n, prec):
 
 
 def run_precision(torch, api, inputs, pr, c_obs, precision, args, steps, warmup, timer,
-                  rtol=None, keep_state=False):
+                  rtol=None, keep_state=False, kernel_rates=False):
     plan = api.Plan(pr.n, pr.nt, pr.centres, pr.sigma, T=pr.T,
                     rtol=args.rtol if rtol is None else rtol,
                     ckpt_stride=args.ckpt, precision=precision)
@@ -109,8 +111,11 @@ def run_precision(torch, api, inputs, pr, c_obs, precision, args, steps, warmup,
     t0 = time.perf_counter()
     e0.record(st)
     out = None
+    step_ms = []
     for _ in range(steps):
-        out = step()
+        ts = time.perf_counter()
+        out = step()  # ends with a synchronizing stats read
+        step_ms.append(1000.0 * (time.perf_counter() - ts))
     e1.record(st)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -119,6 +124,8 @@ def run_precision(torch, api, inputs, pr, c_obs, precision, args, steps, warmup,
     J, gp, gr, gk, s1, s2 = out
     res = {
         "ms_per_step": 1000.0 * wall / steps,
+        "step_ms_median": sorted(step_ms)[len(step_ms) // 2],
+        "step_ms_min": min(step_ms),
         "event_ms_per_step": ev_ms / steps,
         "value": steps / wall,
         "J": float(J), "g_rho": float(gr), "g_kf": float(gk),
@@ -135,6 +142,20 @@ def run_precision(torch, api, inputs, pr, c_obs, precision, args, steps, warmup,
         ms, launches, work_bytes = tinfo
         res["timer"] = {"kernel": timer, "ms": ms, "launches": launches,
                         "work_bytes": work_bytes}
+    if kernel_rates:
+        # every PCG pass timed over one more forward solve: time per launch
+        # that did work and algorithmic rate
+        es = 4 if precision == "fp32" else 8
+        rates = {}
+        for k, u in KERNEL_FIELDS.items():
+            plan.kernel_timer(k)
+            plan.forward(p, rho, kf, m)
+            ms, launches, work_bytes = plan.kernel_timer_read()
+            work = work_bytes / (u * pr.n ** 3 * es)
+            rates[k] = {"us_per_work_launch": 1000.0 * ms / max(work, 1.0),
+                        "GB_s": work_bytes / (ms * 1e-3) / 1e9, "fields_moved": u}
+        plan.kernel_timer(None)
+        res["kernel_rates"] = rates
     del plan
     torch.cuda.empty_cache()
     return res
@@ -328,8 +349,22 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    # measured device-copy rate (1 GiB, read + write) for the roofline context
+    a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ce0, ce1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ce0.record()
+    for _ in range(5):
+        b.copy_(a)
+    ce1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * (1 << 30) / (ce0.elapsed_time(ce1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+
     r32 = run_precision(torch, api, inputs, pr, c_obs, "fp32", args, args.steps, args.warmup,
-                        args.timer_kernel, keep_state=not args.no_fp64)
+                        args.timer_kernel, keep_state=not args.no_fp64, kernel_rates=True)
     r64 = None
     if not args.no_fp64:
         r64 = run_precision(torch, api, inputs, pr, c_obs, "fp64", args, args.fp64_steps,
@@ -351,7 +386,8 @@ def main():
                 "FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
                 "avg_launch_ms": avg_ms, "launches": t["launches"],
                 "work_launches": t["work_bytes"] / unit,
-                "algorithmic_bytes_per_work_launch": unit}
+                "algorithmic_bytes_per_work_launch": unit,
+                "measured_copy_GB_s": copy_gbs, "frac_of_copy": achieved / copy_gbs}
 
     out = {
         "metric": METRIC,
@@ -377,6 +413,8 @@ def main():
         "roofline": roof,
         "pcg": {k: r32[k] for k in ("pcg_its_forward", "solves_forward", "pcg_its_adjoint",
                                     "solves_adjoint", "pcg_its_max", "worst_rel_residual")},
+        "step_ms_median": r32["step_ms_median"], "step_ms_min": r32["step_ms_min"],
+        "kernel_rates_fp32": r32["kernel_rates"],
     }
     if r64 is not None:
         gp32, gp64 = r32["gp"], r64["gp"]
@@ -394,6 +432,14 @@ def main():
         if not args.no_equal_accuracy:
             out["fp64"]["equal_accuracy"] = equal_accuracy(torch, np, api, inputs, pr, c_obs,
                                                            args, r32)
+    if not args.no_fixed:
+        # the same workload at fixed (rho_f, k_f) = (10, 0.1): PCG iteration
+        # counts grow with k_f, so the seed's k_f alone is not the whole story
+        prf = inputs.problem(args.n, args.g, args.seed, nt=args.nt, T=1.0, rho_f=10.0, k_f=0.1)
+        rf = run_precision(torch, api, inputs, prf, c_obs, "fp32", args, 2, 1, None)
+        out["fixed_params"] = {"rho_f": 10.0, "k_f": 0.1, "value": rf["value"],
+                               "ms_per_step": rf["ms_per_step"],
+                               "pcg_its": rf["pcg_its_forward"] + rf["pcg_its_adjoint"]}
     if not args.no_batch:
         out["batch"] = batch_workload(torch, np, api, inputs, args.batch_reps)
     if not args.no_hvp:
