@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-inversion", action="store_true",
+                    help="skip the inversion-driver leg")
     ap.add_argument("--no-fixed", action="store_true",
                     help="skip the (rho_f, k_f) = (10, 0.1) leg")
     ap.add_argument("--no-equal-accuracy", action="store_true",
@@ -199,6 +201,50 @@ def equal_accuracy(torch, np, api, inputs, pr, c_obs, args, r32):
         res.update({"fp64_rtol": rt, "fp64_err": e, "fp64_s": r["ms_per_step"] / 1000.0,
                     "speedup": r["ms_per_step"] / r32["ms_per_step"]})
     return res
+
+
+def inversion_workload(torch, np, api, inputs):
+    """The two-phase inversion driver (l1 phase with Hoyer-driven beta
+    continuation, then weighted-l2 L-BFGS over p and k_f) on the FP32-mixed
+    gradient at 128^3: 64 Gaussians of which two are active in the data,
+    rho_f = 10, k_f = 0.1 to recover, nt = 16.  The data are the FP64
+    path's c(T) at rtol 1e-10."""
+    from paper_1907_07774_amd import inversion
+    pr = inputs.problem(128, 4, 2, nt=16, rho_f=10.0, k_f=0.1)
+    rng = np.random.default_rng(77)
+    active = rng.choice(pr.p.size, 2, replace=False)
+    p_true = np.zeros_like(pr.p)
+    p_true[active] = (0.9, 0.7)
+    dev = torch.device("cuda:0")
+    ref = api.Plan(pr.n, pr.nt, pr.centres, pr.sigma, rtol=1e-10, precision="fp64")
+    d = ref.forward(torch.tensor(p_true, device=dev), pr.rho_f, pr.k_f,
+                    torch.tensor(pr.m, dtype=torch.float64, device=dev)).float()
+    del ref
+    torch.cuda.empty_cache()
+    plan = api.Plan(pr.n, pr.nt, pr.centres, pr.sigma, rtol=1e-8, precision="fp32")
+    obj = inversion.GpuMisfit(plan, pr.m, d, pr.rho_f)
+    cfg = inversion.InversionConfig(bisections=4, maxit_gist=30, opttol=1e-3, maxit_l2=50)
+    D0 = obj(np.zeros(pr.p.size), 0.05)[0]
+    obj.evaluations = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = inversion.invert(obj, pr.p.size, cfg)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    top = set(int(i) for i in np.argsort(-np.abs(res.p))[:2])
+    out = {"workload": "128^3, 64 Gaussians (2 active), rho_f = 10, k_f = 0.1, nt = 16, "
+                       "FP32-mixed gradient; l1 phase (4 beta steps, <= 30 GIST iterations "
+                       "each) + weighted-l2 L-BFGS (opttol 1e-3)",
+           "seconds": sec, "gradient_evaluations": obj.evaluations,
+           "evaluations_per_s": obj.evaluations / sec,
+           "l1_iterations": res.l1_iterations, "l2_iterations": res.l2_iterations,
+           "misfit_reduction": res.misfit / D0, "k_f": res.k_f,
+           "k_f_rel_err": abs(res.k_f - pr.k_f) / pr.k_f,
+           "active_recovered": top == set(int(i) for i in active),
+           "grad_rel": res.grad_rel, "converged": res.converged}
+    del plan, obj
+    torch.cuda.empty_cache()
+    return out
 
 
 def batch_workload(torch, np, api, inputs, reps):
@@ -440,6 +486,8 @@ def main():
         out["fixed_params"] = {"rho_f": 10.0, "k_f": 0.1, "value": rf["value"],
                                "ms_per_step": rf["ms_per_step"],
                                "pcg_its": rf["pcg_its_forward"] + rf["pcg_its_adjoint"]}
+    if not args.no_inversion:
+        out["inversion"] = inversion_workload(torch, np, api, inputs)
     if not args.no_batch:
         out["batch"] = batch_workload(torch, np, api, inputs, args.batch_reps)
     if not args.no_hvp:

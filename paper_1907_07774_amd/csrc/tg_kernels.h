@@ -921,11 +921,14 @@ enum FinMode : int {
   FIN_MMAX = 6    // slot: partial max(m)
 };
 
-template <int MODE>
-__global__ void __launch_bounds__(256)
+// One workgroup of NT threads per problem (NT = 1024 for the PCG-loop
+// finalizers, whose partial sums come from thousands of workgroups).
+template <int MODE, int NT = 256>
+__global__ void __launch_bounds__(NT)
 k_finalize(ProbScalars* __restrict__ sc, const double* __restrict__ part, int nblk,
            double scale_, double rtol, int maxit, int nblk2 = 0) {
-  __shared__ double red[NSLOT * 4];
+  constexpr int NW = NT / 64;
+  __shared__ double red[NSLOT * NW];
   const int b = blockIdx.x;
   ProbScalars& S = sc[b];
   if ((MODE == FIN_PAP || MODE == FIN_RZ) && S.done) return;
@@ -933,13 +936,13 @@ k_finalize(ProbScalars* __restrict__ sc, const double* __restrict__ part, int nb
   double acc[NSLOT] = {0.0, 0.0, 0.0, 0.0};
   if constexpr (MODE == FIN_MMAX) {
     double mx = 0.0;
-    for (int i = threadIdx.x; i < nblk; i += 256) mx = fmax(mx, part_at((double*)part, b, 0)[i]);
+    for (int i = threadIdx.x; i < nblk; i += NT) mx = fmax(mx, part_at((double*)part, b, 0)[i]);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
     __syncthreads();
     if (threadIdx.x == 0) {
-      mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+      for (int w = 0; w < NW; ++w) mx = fmax(mx, red[w]);
       S.mmax = mx;
       S.kbar = S.kf * mx;
     }
@@ -947,9 +950,9 @@ k_finalize(ProbScalars* __restrict__ sc, const double* __restrict__ part, int nb
   }
   for (int s = 0; s < ns; ++s) {
     const int nb = (MODE == FIN_PAP && s == 1) ? nblk2 : nblk;
-    for (int i = threadIdx.x; i < nb; i += 256) acc[s] += part_at((double*)part, b, s)[i];
+    for (int i = threadIdx.x; i < nb; i += NT) acc[s] += part_at((double*)part, b, s)[i];
   }
-  block_sums<256>(acc, ns, red);
+  block_sums<NT>(acc, ns, red);
   if (threadIdx.x != 0) return;
   if constexpr (MODE == FIN_INIT) {
     S.rhs2 = acc[0] * scale_;

@@ -397,13 +397,14 @@ class Solver final : public ISolver {
       sch_.x_inv_grad(1, c.P, c.R, c.T1, c.T2, c.sc, c.part, tau_, 1, c.nb, st_);
     });
     matvec_mid(c, c.T1, c.T2, c.T3, 1);
-    k_finalize<FIN_PAP><<<c.nb, 256, 0, st_>>>(c.sc, c.part, sch_.xi_nblk, tau_ * (double)REAL,
-                                               rtol(), maxit(), sch_.zm_nblk);
+    k_finalize<FIN_PAP, 1024><<<c.nb, 1024, 0, st_>>>(c.sc, c.part, sch_.xi_nblk,
+                                                     tau_ * (double)REAL, rtol(), maxit(),
+                                                     sch_.zm_nblk);
     timed(KT_X_FWD_DIV, 0, [&] {
       sch_.x_fwd_div(XM_PCG, c.T1, c.T2, c.X, c.R, c.P, c.sc, c.part, tau_, 1, 0, c.nb, st_);
     });
-    k_finalize<FIN_RZ><<<c.nb, 256, 0, st_>>>(c.sc, c.part, sch_.xf_nblk, 1.0 / REAL, rtol(),
-                                              maxit());
+    k_finalize<FIN_RZ, 1024><<<c.nb, 1024, 0, st_>>>(c.sc, c.part, sch_.xf_nblk, 1.0 / REAL,
+                                                    rtol(), maxit());
   }
 
   // ------------------------------------------------------ kernel timer
