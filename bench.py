@@ -223,7 +223,11 @@ def inversion_workload(torch, np, api, inputs):
     torch.cuda.empty_cache()
     plan = api.Plan(pr.n, pr.nt, pr.centres, pr.sigma, rtol=1e-8, precision="fp32")
     obj = inversion.GpuMisfit(plan, pr.m, d, pr.rho_f)
-    cfg = inversion.InversionConfig(bisections=4, maxit_gist=30, opttol=1e-3, maxit_l2=50)
+    # the reference gradient is taken at p = 0, where the linearized growth
+    # is e^{rho_f T} = e^10: opttol 1e-5 here asks what 1e-3 asks at the
+    # paper's rho_f T of about 2.4
+    cfg = inversion.InversionConfig(bisections=4, maxit_gist=30, opttol=1e-5, maxit_l2=150,
+                                    outer=2)
     D0 = obj(np.zeros(pr.p.size), 0.05)[0]
     obj.evaluations = 0
     torch.cuda.synchronize()
@@ -233,8 +237,9 @@ def inversion_workload(torch, np, api, inputs):
     sec = time.perf_counter() - t0
     top = set(int(i) for i in np.argsort(-np.abs(res.p))[:2])
     out = {"workload": "128^3, 64 Gaussians (2 active), rho_f = 10, k_f = 0.1, nt = 16, "
-                       "FP32-mixed gradient; l1 phase (4 beta steps, <= 30 GIST iterations "
-                       "each) + weighted-l2 L-BFGS (opttol 1e-3)",
+                       "FP32-mixed gradient; two passes of: l1 phase (4 beta steps, <= 30 "
+                       "GIST iterations each) + weighted-l2 L-BFGS (opttol 1e-5, <= 150 "
+                       "iterations)",
            "seconds": sec, "gradient_evaluations": obj.evaluations,
            "evaluations_per_s": obj.evaluations / sec,
            "l1_iterations": res.l1_iterations, "l2_iterations": res.l2_iterations,

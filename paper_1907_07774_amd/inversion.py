@@ -17,6 +17,10 @@ tumor model for fixed rho_f, healthy white matter m and observation d:
    line search until the gradient norm falls below opttol times the norm
    of the gradient at p = 0.
 
+The paper alternates the two phases inside its outer (Picard) iteration,
+each l1 phase holding k_f at the last l2 estimate; ``outer`` repeats the
+pair that way without the registration step between them.
+
 Every objective evaluation is one forward and one adjoint solve through the
 C-ABI (``GpuMisfit``); the optimizer works on a few dozen float64 numbers on
 the host.  Any callable with the same signature can stand in for the
@@ -24,11 +28,13 @@ objective.
 """
 from __future__ import annotations
 
+import math
 from dataclasses import dataclass, field
 
 import numpy as np
 
 from . import optim
+from ._lib import TG_ERR_NOT_CONVERGED, TG_ERR_NUMERIC, TumorGradError
 
 
 class GpuMisfit:
@@ -45,15 +51,25 @@ class GpuMisfit:
         self.d = torch.as_tensor(d, dtype=dt, device=plan.device).contiguous()
         self.rho = torch.tensor([float(rho_f)], dtype=torch.float64, device=plan.device)
         self.evaluations = 0
+        self.failures = 0
 
     def __call__(self, p, k_f):
         import torch
         dev = self.plan.device
         pt = torch.as_tensor(np.asarray(p, dtype=np.float64), device=dev)
         kt = torch.tensor([float(k_f)], dtype=torch.float64, device=dev)
-        self.plan.forward(pt, self.rho, kt, self.m)
-        J, gp, _, gk = self.plan.adjoint_misfit(self.d)
         self.evaluations += 1
+        try:
+            self.plan.forward(pt, self.rho, kt, self.m)
+            J, gp, _, gk = self.plan.adjoint_misfit(self.d)
+        except TumorGradError as e:
+            # a trial point where a solve broke down or went non-finite (e.g.
+            # c^0 below the pole -1/(E-1) of the logistic step) is outside
+            # the objective's domain: the line search backs off from it
+            if e.status not in (TG_ERR_NOT_CONVERGED, TG_ERR_NUMERIC):
+                raise
+            self.failures += 1
+            return math.inf, np.full(len(p), np.nan), math.nan
         return float(J), gp.cpu().numpy().astype(np.float64), float(gk)
 
 
@@ -77,7 +93,10 @@ class InversionConfig:
     k_f_init: float = 0.05        # k_f starting value of the l2 phase if k_f0 = 0
     k_f_min: float = 1e-4         # lower bound kept by the l2 line search
     k_scale: float = 0.1          # k_f is optimized as k_f / k_scale
+    max_dp: float = 1.0           # largest change of any p_i in one l2 step
     skip_l1: bool = False         # start the l2 phase from p0 directly
+    outer: int = 1                # l1 + l2 passes; each later l1 phase keeps
+                                  # k_f at the previous l2 estimate
 
 
 @dataclass
@@ -153,10 +172,16 @@ def l2_phase(obj, p0, k0, w, g_ref_norm, cfg: InversionConfig):
         g[n] = gk * ks
         return f, g
 
-    def stpmax(x, d):  # keep k_f >= k_f_min
-        if d[n] >= 0.0:
-            return 1e20
-        return max((x[n] - cfg.k_f_min / ks) / (-d[n]), 1e-12)
+    def stpmax(x, d):
+        # keep k_f >= k_f_min and move no p_i by more than max_dp: a long
+        # step in p can push c^0 = Phi p past the logistic step's pole
+        s = 1e20
+        dp = float(np.abs(d[:n]).max())
+        if dp > 0.0:
+            s = cfg.max_dp / dp
+        if d[n] < 0.0:
+            s = min(s, max((x[n] - cfg.k_f_min / ks) / (-d[n]), 1e-12))
+        return s
 
     x0 = np.concatenate([p0, [k0 / ks]])
     gref = np.zeros(n + 1)
@@ -175,21 +200,27 @@ def invert(obj, n_p, cfg: InversionConfig | None = None, p0=None) -> InversionRe
     g_ref = float(np.linalg.norm(g_zero))
     res = InversionResult(p=p0, k_f=cfg.k_f0, objective=np.nan, misfit=np.nan,
                           grad_rel=np.nan, evaluations=1)
-    if cfg.skip_l1:
-        p_l1 = p0
-        w = np.full(n_p, cfg.w_small)
-    else:
-        p_l1, betas, hs, its, nev = l1_phase(obj, p0, cfg.k_f0, cfg)
-        res.l1_betas, res.l1_hoyer, res.l1_iterations = betas, hs, its
-        res.evaluations += nev
-        w = l2_weights(p_l1, cfg)
+    k_l1 = cfg.k_f0
     k0 = cfg.k_f0 if cfg.k_f0 > 0 else cfg.k_f_init
-    r, p, k = l2_phase(obj, p_l1, k0, w, g_ref, cfg)
+    for _ in range(max(1, cfg.outer)):
+        if cfg.skip_l1:
+            p_l1 = p0
+            w = np.full(n_p, cfg.w_small)
+        else:
+            # every l1 phase starts from p0: its beta range comes from the
+            # gradient there
+            p_l1, betas, hs, its, nev = l1_phase(obj, p0, k_l1, cfg)
+            res.l1_betas, res.l1_hoyer = betas, hs
+            res.l1_iterations += its
+            res.evaluations += nev
+            w = l2_weights(p_l1, cfg)
+        r, p, k = l2_phase(obj, p_l1, k0, w, g_ref, cfg)
+        res.l2_iterations += r.iterations
+        res.evaluations += r.evaluations
+        k_l1 = k0 = k
     D = r.f - 0.5 * cfg.beta_p * float((w * p) @ p)
     res.p, res.k_f, res.objective, res.misfit = p, k, r.f, D
     res.grad_rel = float(np.linalg.norm(r.g)) / g_ref if g_ref > 0 else 0.0
-    res.l2_iterations = r.iterations
-    res.evaluations += r.evaluations
     res.converged = r.converged
     res.weights = w
     return res

@@ -102,6 +102,13 @@ def more_thuente(phi, f0, g0, stp=1.0, ftol=1e-4, gtol=0.9, xtol=1e-10,
     phi(s) returns (value, derivative) along the direction.  Returns
     (step, value, derivative, evaluations, info) with info 'ok',
     'maxfev', 'xtol' or 'bounds' (then the best step found).
+
+    A trial with a non-finite value or derivative, or one above phi(0)
+    whose slope is negative and steeper than 1000 phi'(0), lies past a
+    singularity of phi (the method assumes phi smooth): the upper bound
+    drops to the midpoint between it and the best step, which is tried
+    next; 'domain' is returned with the best step if maxfev runs out that
+    way.
     """
     if g0 >= 0.0:
         raise ValueError("not a descent direction")
@@ -118,6 +125,15 @@ def more_thuente(phi, f0, g0, stp=1.0, ftol=1e-4, gtol=0.9, xtol=1e-10,
     while True:
         f, g = phi(stp)
         nfev += 1
+        # a non-finite trial, or one above phi(0) whose slope is still
+        # negative and a thousand times steeper than at 0, has a singularity
+        # of phi between it and the best step; the cubic and quadratic models
+        # are meaningless across it, so halve toward the best step instead
+        if not (math.isfinite(f) and math.isfinite(g)) or (f > f0 and g < 1e3 * g0):
+            if nfev >= maxfev:
+                return stx, fx, gx, nfev, "domain"
+            stp = stpmax = max(stx + 0.5 * (stp - stx), stpmin)
+            continue
         ftest = f0 + stp * ftest_slope
         if f <= ftest and abs(g) <= gtol * (-g0):
             return stp, f, g, nfev, "ok"
@@ -183,6 +199,8 @@ def lbfgs(fg, x0, gtol_rel=1e-6, g_ref=None, maxit=200, memory=10, stpmax_fn=Non
     x = np.array(x0, dtype=np.float64)
     f, g = fg(x)
     nev = 1
+    if not (math.isfinite(f) and np.all(np.isfinite(g))):
+        raise ValueError("objective is not finite at the starting point")
     gref = np.linalg.norm(g if g_ref is None else g_ref)
     S, Y = [], []
     hist = [(f, float(np.linalg.norm(g)))]
@@ -214,17 +232,28 @@ def lbfgs(fg, x0, gtol_rel=1e-6, g_ref=None, maxit=200, memory=10, stpmax_fn=Non
             g0 = float(g @ d)
         stpmax = stpmax_fn(x, d) if stpmax_fn else 1e20
 
+        seen = {}
+
         def phi(t):
             nonlocal nev
             ft, gt = fg(x + t * d)
             nev += 1
-            phi.last = gt
+            seen[t] = gt
             return ft, float(gt @ d)
 
         stp, fn, _, _, info = more_thuente(phi, f, g0, stp=min(1.0, 0.99 * stpmax),
                                            stpmax=stpmax)
+        if not fn < f:
+            # no decrease along d (the search ended at its lower bound or on
+            # noise): drop the curvature pairs and retry along steepest
+            # descent; stop if that direction fails too
+            if not S:
+                break
+            S.clear()
+            Y.clear()
+            continue
         xn = x + stp * d
-        gn = phi.last
+        gn = seen[stp]
         s, y = xn - x, gn - g
         if float(s @ y) > 1e-12 * float(np.linalg.norm(s) * np.linalg.norm(y)):
             S.append(s)
@@ -238,8 +267,6 @@ def lbfgs(fg, x0, gtol_rel=1e-6, g_ref=None, maxit=200, memory=10, stpmax_fn=Non
             callback(it, x, f, g)
         if np.linalg.norm(g) <= gtol_rel * gref:
             return OptResult(x, f, g, it, nev, True, hist)
-        if info != "ok" and stp == 0.0:
-            break
     return OptResult(x, f, g, it, nev, False, hist)
 
 

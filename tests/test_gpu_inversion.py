@@ -60,10 +60,12 @@ def test_l2_phase_on_gpu_matches_oracle_minimizer(case16):
 
 
 def test_two_phase_inversion_fp32_64():
-    """Sparse initial condition (2 of 27 Gaussians), rho_f = 10, k_f = 0.1,
-    64^3, nt = 8, FP32-mixed path: the misfit falls by three orders of
-    magnitude, the active Gaussians are the largest coefficients and k_f
-    comes back within 10%."""
+    """Two adjacent active Gaussians (2 of 27; the paper's synthetic
+    targets enable two nearby ones), rho_f = 10, k_f = 0.1, 64^3, nt = 8,
+    FP32-mixed path, two l1 + l2 passes (the second l1 phase at the first
+    l2 estimate of k_f): the misfit falls by three orders of magnitude, the
+    active Gaussians are the largest coefficients, k_f comes back within
+    10% and the last l2 phase meets its gradient tolerance."""
     print("case inversion two-phase fp32 64^3", flush=True)
     pr = inputs.problem(64, 3, 21, nt=8, rho_f=10.0, k_f=0.1)
     p_true = np.zeros_like(pr.p)
@@ -72,9 +74,14 @@ def test_two_phase_inversion_fp32_64():
     d = tumor.forward(su, p_true).c[-1]
     plan = api.Plan(64, pr.nt, pr.centres, pr.sigma, rtol=1e-8, precision="fp32")
     obj = inversion.GpuMisfit(plan, pr.m, d, pr.rho_f)
-    cfg = inversion.InversionConfig(bisections=4, maxit_gist=40, opttol=1e-4, maxit_l2=60)
+    cfg = inversion.InversionConfig(bisections=4, maxit_gist=40, opttol=1e-4, maxit_l2=150,
+                                    outer=2)
     res = inversion.invert(obj, pr.p.size, cfg)
     D0 = obj(np.zeros(pr.p.size), 0.05)[0]
+    print(f"misfit {res.misfit:.3e} (D0 {D0:.3e}) k_f {res.k_f:.4f} "
+          f"top {np.argsort(-np.abs(res.p))[:3]} evals {res.evaluations}", flush=True)
+    assert obj.failures == 0
+    assert res.converged
     assert res.misfit < 1e-3 * D0
     assert set(np.argsort(-np.abs(res.p))[:2]) == {4, 13}
     assert abs(res.k_f - 0.1) < 0.01

@@ -202,3 +202,37 @@ def test_two_phase_driver_on_oracle(oracle_case):
     assert abs(res.p[2] - 0.8) < 0.05
     assert abs(res.k_f - 0.15) < 0.02
     assert res.grad_rel < 1e-4 or res.l2_iterations == cfg.maxit_l2
+
+
+def test_more_thuente_backs_off_outside_the_domain():
+    """phi = (s - 2)^2 - 4 is undefined past s = 3: started at s = 10 the
+    search halves back into the domain and still meets the strong Wolfe
+    conditions."""
+    def phi(s):
+        if s > 3.0:
+            return math.inf, math.nan
+        return (s - 2) ** 2 - 4, 2 * (s - 2)
+    f0, g0 = phi(0.0)
+    stp, f, g, nfev, info = optim.more_thuente(phi, f0, g0, stp=10.0, ftol=1e-4, gtol=0.5)
+    assert info == "ok" and stp <= 3.0
+    assert f <= f0 + 1e-4 * stp * g0 and abs(g) <= 0.5 * abs(g0)
+
+
+
+def test_more_thuente_backs_off_across_a_pole():
+    """phi = (s - 0.2)^2 + eps (1/s0 - 1/(s0 - s)) has a pole at s0 = 0.4:
+    just past it the value is above phi(0) and the slope is negative and
+    thousands of times steeper.  The search halves back below the pole and
+    meets the strong Wolfe conditions there instead of interpolating
+    across it."""
+    s0, eps = 0.4, 1e-4
+
+    def phi(s):
+        return ((s - 0.2) ** 2 + eps * (1 / s0 - 1 / (s0 - s)),
+                2 * (s - 0.2) - eps / (s0 - s) ** 2)
+    f0, g0 = phi(0.0)
+    f1, g1 = phi(0.4001)
+    assert f1 > f0 and g1 < 1e3 * g0   # the guard's condition holds there
+    stp, f, g, nfev, info = optim.more_thuente(phi, f0, g0, stp=0.4001, ftol=1e-4, gtol=0.9)
+    assert info == "ok" and stp < s0 and nfev == 2
+    assert f <= f0 + 1e-4 * stp * g0 and abs(g) <= 0.9 * abs(g0)
