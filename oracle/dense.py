@@ -66,11 +66,13 @@ def _R(u, m, rho, tau):
     return u * E / (1.0 + u * (E - 1.0))
 
 
-def forward(m, centres, sigma, p, rho_f, k_f, nt, T=1.0):
+def forward(m, centres, sigma, p, rho_f, k_f, nt, T=1.0, m_rho=None, mask=None):
     """Dense Strang/Crank-Nicolson forward map; returns the list c^0..c^nt
-    (flattened).  Parameters may be complex (complex-step)."""
+    (flattened).  Parameters may be complex (complex-step).  m drives the
+    diffusion, m_rho (default m) the reaction; c^0 = diag(mask) Phi p."""
     n = m.shape[0]
     mf = m.ravel()
+    mr = mf if m_rho is None else m_rho.ravel()
     Ds = derivative_3d(n)
     dt = T / nt
     tau = 0.5 * dt
@@ -78,36 +80,49 @@ def forward(m, centres, sigma, p, rho_f, k_f, nt, T=1.0):
     I = np.eye(n ** 3)
     L = I - tau * A
     Rm = I + tau * A
-    c = basis_matrix(centres, sigma, n) @ np.asarray(p)
+    Phi = basis_matrix(centres, sigma, n)
+    if mask is not None:
+        Phi = mask.ravel()[:, None] * Phi
+    c = Phi @ np.asarray(p)
     cs = [c]
     for _ in range(nt):
-        a = _R(c, mf, rho_f, tau)
+        a = _R(c, mr, rho_f, tau)
         b = np.linalg.solve(L, Rm @ a)
-        c = _R(b, mf, rho_f, tau)
+        c = _R(b, mr, rho_f, tau)
         cs.append(c)
     return cs
 
 
-def objective(m, centres, sigma, p, rho_f, k_f, nt, d, T=1.0):
-    """J = 1/2 h^3 sum (c(T) - d)^2 (written without abs so it stays
-    analytic for complex-step)."""
+def objective(m, centres, sigma, p, rho_f, k_f, nt, d, T=1.0, m_rho=None, mask=None,
+              labels=None):
+    """J = 1/2 h^3 sum (c(T) - d)^2, plus 1/2 h^3 sum_i sum (m_i (1 - c(T))
+    - mP_i)^2 if labels = (m_lab, m_pat) is given (written without abs so
+    it stays analytic for complex-step)."""
     n = m.shape[0]
     h3 = (TWO_PI / n) ** 3
-    r = forward(m, centres, sigma, p, rho_f, k_f, nt, T)[-1] - d.ravel()
-    return 0.5 * h3 * np.sum(r * r)
+    c = forward(m, centres, sigma, p, rho_f, k_f, nt, T, m_rho, mask)[-1]
+    r = c - d.ravel()
+    J = 0.5 * h3 * np.sum(r * r)
+    if labels is not None:
+        for mi, pi in zip(*labels):
+            e = mi.ravel() * (1.0 - c) - pi.ravel()
+            J = J + 0.5 * h3 * np.sum(e * e)
+    return J
 
 
-def complex_step_gradient(m, centres, sigma, p, rho_f, k_f, nt, d, T=1.0, h=1e-30):
+def complex_step_gradient(m, centres, sigma, p, rho_f, k_f, nt, d, T=1.0, h=1e-30,
+                          m_rho=None, mask=None, labels=None):
     """Gradient of J with respect to (p, rho_f, k_f) by the complex-step
     method: dJ/dx = Im J(x + i h e) / h."""
+    kw = dict(m_rho=m_rho, mask=mask, labels=labels)
     p = np.asarray(p, dtype=np.float64)
     gp = np.empty_like(p)
     for i in range(p.size):
         pp = p.astype(np.complex128)
         pp[i] += 1j * h
-        gp[i] = objective(m, centres, sigma, pp, rho_f, k_f, nt, d, T).imag / h
-    g_rho = objective(m, centres, sigma, p, rho_f + 1j * h, k_f, nt, d, T).imag / h
-    g_k = objective(m, centres, sigma, p, rho_f, k_f + 1j * h, nt, d, T).imag / h
+        gp[i] = objective(m, centres, sigma, pp, rho_f, k_f, nt, d, T, **kw).imag / h
+    g_rho = objective(m, centres, sigma, p, rho_f + 1j * h, k_f, nt, d, T, **kw).imag / h
+    g_k = objective(m, centres, sigma, p, rho_f, k_f + 1j * h, nt, d, T, **kw).imag / h
     return gp, float(g_rho), float(g_k)
 
 

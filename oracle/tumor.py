@@ -34,6 +34,17 @@ term in the continuous adjoint is not used; the discrete transpose fixes it.
 Objective: J = 1/2 ||c(T) - d||^2_{L2} approximated by the periodic
 trapezoid rule, J = 1/2 h^3 sum (c(T) - d)^2 (tumor misfit of Tab. 1).
 
+Full coefficient and misfit model (Sec. 2.1): the diffusion and reaction
+coefficients are tissue-weighted sums k = k_f sum_i k_i m_i and
+rho = rho_f sum_i rho_i m_i over the WM/GM/CSF maps, so the diffusion field
+m (``Setup.m``) and the reaction field (``Setup.m_rho``, default m) may
+differ; the Gaussians are zero inside CSF, c(0) = w Phi p with a mask field
+w (``Setup.phi_mask``, default 1; ``csf_mask`` gives w = 1 - m_CSF); and
+the objective may add the anatomy-label misfit
+D_m = 1/2 ||m (1 - c(T)) - m_P||^2 of the tumor-masked healthy labels
+against the patient's (``misfit_labels``), whose derivative enters the
+adjoint's terminal condition.
+
 Parity pins: see tests/test_oracle_*.py (closed forms, invariants, dense 8^3
 brute force with complex-step derivatives, finite differences).
 """
@@ -115,10 +126,20 @@ class Setup:
     T: float = 1.0
     rtol: float = 1e-13
     maxit: int = 2000
+    m_rho: np.ndarray | None = None     # reaction field (default: m)
+    phi_mask: np.ndarray | None = None  # c(0) = phi_mask * Phi p (default 1)
 
     @property
     def n(self):
         return self.m.shape[0]
+
+    @property
+    def mr(self):
+        """Field of the reaction coefficient rho = rho_f mr."""
+        return self.m if self.m_rho is None else self.m_rho
+
+    def masked(self, field):
+        return field if self.phi_mask is None else self.phi_mask * field
 
     @property
     def dt(self):
@@ -175,8 +196,9 @@ class Trajectory:
 
 
 def forward(setup: Setup, p) -> Trajectory:
-    """State solve: Strang steps from c0 = Phi p to c(T)."""
-    return forward_c0(setup, phi(p, setup.centres, setup.sigma, setup.n))
+    """State solve: Strang steps from c0 = Phi p (times the CSF mask, if
+    set) to c(T)."""
+    return forward_c0(setup, setup.masked(phi(p, setup.centres, setup.sigma, setup.n)))
 
 
 def forward_c0(setup: Setup, c0) -> Trajectory:
@@ -185,10 +207,10 @@ def forward_c0(setup: Setup, c0) -> Trajectory:
     c = np.array(c0, dtype=np.float64, copy=True)
     tr = Trajectory([c], [], [], [])
     for _ in range(setup.nt):
-        a = reaction(c, setup.m, setup.rho_f, tau)
+        a = reaction(c, setup.mr, setup.rho_f, tau)
         rhs = a + tau * setup.k_f * _A_m(setup, a)
         b, its = _cn_solve(setup, rhs, a)
-        c = reaction(b, setup.m, setup.rho_f, tau)
+        c = reaction(b, setup.mr, setup.rho_f, tau)
         tr.a.append(a)
         tr.b.append(b)
         tr.c.append(c)
@@ -200,6 +222,35 @@ def misfit(setup: Setup, cT, d):
     """J = 1/2 h^3 sum (c(T) - d)^2 and its gradient h^3 (c(T) - d)."""
     r = cT - d
     return 0.5 * setup.h3 * float(np.sum(r * r)), setup.h3 * r
+
+
+def misfit_labels(setup: Setup, cT, d, m_lab, m_pat):
+    """J = D_c + D_m with D_m = 1/2 h^3 sum_x sum_i (m_i (1 - c) - mP_i)^2
+    (Sec. 2.1 objective: the simulated tumor masks the healthy labels
+    m_i, which are compared with the patient's labels mP_i), and its
+    gradient in c(T):  h^3 [(c - d) - sum_i m_i (m_i (1 - c) - mP_i)].
+    m_lab, m_pat: sequences of label fields."""
+    J, lam = misfit(setup, cT, d)
+    for mi, pi in zip(m_lab, m_pat):
+        e = mi * (1.0 - cT) - pi
+        J += 0.5 * setup.h3 * float(np.sum(e * e))
+        lam = lam - setup.h3 * mi * e
+    return J, lam
+
+
+def coefficient_fields(tissues, k_w, rho_w):
+    """Diffusion and reaction fields of the tissue-weighted coefficient
+    model (Sec. 2.1): k = k_f sum_i k_i m_i, rho = rho_f sum_i rho_i m_i.
+    Returns (sum_i k_i m_i, sum_i rho_i m_i)."""
+    mk = sum(w * t for w, t in zip(k_w, tissues))
+    mr = sum(w * t for w, t in zip(rho_w, tissues))
+    return np.asarray(mk, dtype=np.float64), np.asarray(mr, dtype=np.float64)
+
+
+def csf_mask(m_csf):
+    """Mask of the initial condition: the Gaussians vanish where the
+    tissue is CSF (Sec. 2.1); with a probability map, w = 1 - m_CSF."""
+    return 1.0 - np.asarray(m_csf, dtype=np.float64)
 
 
 # ----------------------------------------------------------------- adjoint
@@ -217,7 +268,7 @@ def vjp(setup: Setup, tr: Trajectory, lamT) -> Gradient:
     lamT on c(T) (plain Euclidean pairing).  Returns d<lamT, c(T)>/d(p,
     rho_f, k_f) and the cotangent on c^0."""
     tau = 0.5 * setup.dt
-    m = setup.m
+    m = setup.mr
     lam = np.array(lamT, dtype=np.float64, copy=True)
     g_rho = 0.0
     g_k = 0.0
@@ -236,15 +287,19 @@ def vjp(setup: Setup, tr: Trajectory, lamT) -> Gradient:
         # a = R(c^n)
         g_rho += float(np.sum(lam * reaction_drho(a, m, tau)))
         lam = lam * reaction_du(cn, m, setup.rho_f, tau)
-    g_p = phi_t(lam, setup.centres, setup.sigma)
+    g_p = phi_t(setup.masked(lam), setup.centres, setup.sigma)
     return Gradient(g_p, g_rho, g_k, lam, its)
 
 
-def gradient(setup: Setup, p, d):
+def gradient(setup: Setup, p, d, labels=None):
     """Reduced gradient of J (Sec. 3.1: state solve, adjoint solve,
-    gradient).  Returns (J, Gradient, Trajectory)."""
+    gradient).  labels = (m_lab, m_pat) adds the label misfit D_m.
+    Returns (J, Gradient, Trajectory)."""
     tr = forward(setup, p)
-    J, lamT = misfit(setup, tr.c[-1], d)
+    if labels is None:
+        J, lamT = misfit(setup, tr.c[-1], d)
+    else:
+        J, lamT = misfit_labels(setup, tr.c[-1], d, *labels)
     return J, vjp(setup, tr, lamT), tr
 
 
@@ -252,7 +307,7 @@ def gradient(setup: Setup, p, d):
 def jvp(setup: Setup, tr: Trajectory, dc0, drho=0.0, dk=0.0):
     """Tangent of c(T) for a perturbation dc0 of c^0 and of rho_f, k_f."""
     tau = 0.5 * setup.dt
-    m = setup.m
+    m = setup.mr
     dc = np.array(dc0, dtype=np.float64, copy=True)
     for n in range(setup.nt):
         cn, a, b, cn1 = tr.c[n], tr.a[n], tr.b[n], tr.c[n + 1]
@@ -266,6 +321,6 @@ def jvp(setup: Setup, tr: Trajectory, dc0, drho=0.0, dk=0.0):
 def gn_hvp(setup: Setup, tr: Trajectory, v):
     """Gauss-Newton Hessian-vector product for J with respect to p:
     H v = Phi^T J_c^T (h^3 I) J_c Phi v, about the trajectory ``tr``."""
-    dc0 = phi(v, setup.centres, setup.sigma, setup.n)
+    dc0 = setup.masked(phi(v, setup.centres, setup.sigma, setup.n))
     dcT = jvp(setup, tr, dc0)
     return vjp(setup, tr, setup.h3 * dcT).g_p

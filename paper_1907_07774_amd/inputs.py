@@ -96,6 +96,50 @@ def phantom(n: int, seed: int) -> np.ndarray:
     return np.clip(m, 0.0, 1.0)
 
 
+def _smooth(raw: np.ndarray) -> np.ndarray:
+    n = raw.shape[0]
+    kk = np.fft.fftfreq(n, 1.0 / n)
+    kr = np.arange(n // 2 + 1, dtype=np.float64)
+    w2 = (kk[:, None, None] ** 2 + kk[None, :, None] ** 2 + kr[None, None, :] ** 2)
+    spec_f = np.fft.rfftn(raw) * np.exp(-0.5 * PHANTOM_SMOOTH ** 2 * w2)
+    return np.fft.irfftn(spec_f, s=(n, n, n), axes=(0, 1, 2))
+
+
+def tissues(n: int, seed: int) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """(WM, GM, CSF) probability maps, each (n, n, n) in [0, 1] with
+    WM + GM + CSF <= 1: the white-matter phantom with two ventricles cut
+    out, gray matter filling the rest of an ellipsoid 1.25x the
+    white-matter one, CSF in the ventricles and in a rim around that
+    ellipsoid (up to 1.4x); smoothed like the phantom.  The ventricle
+    offsets are drawn with the seed."""
+    wm = phantom(n, seed)
+    rng = np.random.default_rng(20_000 + seed)
+    x = grid_coords(n)
+    X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+    a = np.asarray(PHANTOM_AXES)
+    cc = PHANTOM_CENTRE
+
+    def ellipsoid(axes, centre):
+        return ((((X - centre[0]) / axes[0]) ** 2 + ((Y - centre[1]) / axes[1]) ** 2
+                 + ((Z - centre[2]) / axes[2]) ** 2) <= 1.0).astype(np.float64)
+    vent = np.zeros((n, n, n))
+    for side in (-1.0, 1.0):
+        off = rng.uniform(-0.15, 0.15, size=3)
+        ctr = (cc[0] + side * 0.45 + off[0], cc[1] + off[1], cc[2] + off[2])
+        vent = np.maximum(vent, ellipsoid((0.3, 0.7, 0.35), ctr))
+    brain = ellipsoid(1.25 * a, cc)
+    rim = ellipsoid(1.4 * a, cc) - brain
+    vent = np.clip(_smooth(vent), 0.0, 1.0)
+    brain = np.clip(_smooth(brain), 0.0, 1.0)
+    rim = np.clip(_smooth(rim), 0.0, 1.0)
+    wm = wm * (1.0 - vent)
+    csf = np.clip(vent + rim, 0.0, 1.0)
+    gm = np.clip(brain - wm - vent, 0.0, 1.0)
+    total = wm + gm + csf
+    scale = np.where(total > 1.0, 1.0 / np.maximum(total, 1e-300), 1.0)
+    return wm * scale, gm * scale, csf * scale
+
+
 @dataclasses.dataclass(frozen=True)
 class BasisSpec:
     centres: np.ndarray   # (n_p, 3) in [0, 2 pi)

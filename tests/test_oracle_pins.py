@@ -317,6 +317,94 @@ def test_gn_hvp_symmetric_psd(small):
     assert v @ Hv > 0 and w @ Hw > 0
 
 
+# ------------------------------------- full coefficient and misfit model
+K_W, RHO_W = (1.0, 0.1, 0.0), (1.0, 0.3, 0.0)   # WM, GM, CSF weights
+
+
+@pytest.fixture(scope="module")
+def tiny_full():
+    """8^3 with distinct diffusion and reaction fields from WM/GM/CSF maps,
+    the CSF mask on Phi and the label misfit against another seed's
+    tissues."""
+    n, nt = 8, 4
+    pr = inputs.problem(n, 2, 3, nt=nt, rho_f=10.0, k_f=0.1)
+    tis = inputs.tissues(n, 3)
+    pat = inputs.tissues(n, 4)
+    mk, mr = tumor.coefficient_fields(tis, K_W, RHO_W)
+    mask = tumor.csf_mask(tis[2])
+    su = tumor.Setup(mk, pr.centres, pr.sigma, pr.rho_f, pr.k_f, nt, rtol=1e-15,
+                     m_rho=mr, phi_mask=mask)
+    d = inputs.threshold_mask(tumor.forward(su, inputs.perturbed_p(pr.p, 3)).c[-1])
+    assert rel(mk, mr) > 0.1 and float(mask.min()) < 0.5   # the fields differ
+    return pr, su, d, tis, pat
+
+
+def test_coefficient_fields_are_weighted_sums():
+    wm, gm, csf = inputs.tissues(8, 1)
+    mk, mr = tumor.coefficient_fields((wm, gm, csf), (1.0, 0.5, 0.0), (0.0, 0.0, 2.0))
+    assert np.array_equal(mk, wm + 0.5 * gm) and np.array_equal(mr, 2.0 * csf)
+
+
+def test_full_model_forward_matches_dense(tiny_full):
+    pr, su, _, _, _ = tiny_full
+    cs = dense.forward(su.m, pr.centres, pr.sigma, pr.p, pr.rho_f, pr.k_f, pr.nt,
+                       m_rho=su.m_rho, mask=su.phi_mask)
+    tr = tumor.forward(su, pr.p)
+    for k in range(pr.nt + 1):
+        assert rel(tr.c[k], cs[k]) < 1e-12
+
+
+def test_full_model_gradient_matches_dense_complex_step(tiny_full):
+    """Gradient of D_c + D_m in (p, rho_f, k_f) with separate diffusion and
+    reaction fields and the masked basis, against complex-step derivatives
+    of the dense model."""
+    pr, su, d, tis, pat = tiny_full
+    J, g, _ = tumor.gradient(su, pr.p, d, labels=(tis, pat))
+    kw = dict(m_rho=su.m_rho, mask=su.phi_mask, labels=(tis, pat))
+    gp, gr, gk = dense.complex_step_gradient(su.m, pr.centres, pr.sigma, pr.p, pr.rho_f,
+                                             pr.k_f, pr.nt, d, **kw)
+    Jd = dense.objective(su.m, pr.centres, pr.sigma, pr.p, pr.rho_f, pr.k_f, pr.nt, d, **kw)
+    assert abs(J - Jd) < 1e-11 * abs(Jd)
+    assert rel(g.g_p, gp) < 1e-11
+    assert abs(g.g_rho - gr) < 1e-11 * abs(gr)
+    assert abs(g.g_k - gk) < 1e-11 * abs(gk)
+    # the label term matters: without it the gradient is far off
+    J0, g0, _ = tumor.gradient(su, pr.p, d)
+    assert J - J0 > 1e-3 * J and rel(g0.g_p, gp) > 1e-3
+
+
+def test_reaction_field_drives_the_reaction():
+    """k_f = 0 with distinct fields: c(T) solves dc/dt = rho_f mr c (1 - c)
+    from c0 = w Phi p pointwise (ODE integration), whatever the diffusion
+    field is."""
+    n, nt, rho = 8, 4, 10.0
+    wm, gm, csf = inputs.tissues(n, 2)
+    mk, mr = tumor.coefficient_fields((wm, gm, csf), (1.0, 0.0, 0.0), (0.3, 1.0, 0.1))
+    mask = tumor.csf_mask(csf)
+    rng = np.random.default_rng(6)
+    cen = rng.uniform(0, TWO_PI, (5, 3))
+    p = rng.uniform(0.2, 1.0, 5)
+    su = tumor.Setup(mk, cen, 0.8, rho, 0.0, nt, m_rho=mr, phi_mask=mask)
+    c0 = mask * tumor.phi(p, cen, 0.8, n)
+    cT = tumor.forward(su, p).c[-1]
+    idx = rng.choice(n ** 3, 64, replace=False)
+    mm, y0 = mr.ravel()[idx], c0.ravel()[idx]
+    sol = solve_ivp(lambda t, y: rho * mm * y * (1 - y), (0, 1), y0,
+                    method="DOP853", rtol=1e-13, atol=1e-15)
+    assert np.abs(sol.y[:, -1] - cT.ravel()[idx]).max() < 1e-10
+
+
+def test_csf_mask_reduces_to_plain_basis_and_zeroes_csf():
+    pr = inputs.problem(8, 2, 3, nt=2, rho_f=10.0, k_f=0.1)
+    su1 = tumor.Setup(pr.m, pr.centres, pr.sigma, pr.rho_f, pr.k_f, 2, phi_mask=np.ones((8,) * 3))
+    su0 = tumor.Setup(pr.m, pr.centres, pr.sigma, pr.rho_f, pr.k_f, 2)
+    assert np.array_equal(tumor.forward(su1, pr.p).c[0], tumor.forward(su0, pr.p).c[0])
+    csf = np.zeros((8,) * 3)
+    csf[2:5, 1:6, 3:7] = 1.0
+    su = tumor.Setup(pr.m, pr.centres, pr.sigma, pr.rho_f, pr.k_f, 2, phi_mask=tumor.csf_mask(csf))
+    assert np.all(tumor.forward(su, pr.p).c[0][csf == 1.0] == 0.0)
+
+
 # ----------------------------------------------- mutations must be caught
 def _mutant_gradient_error(monkeypatch, name, fn, tiny):
     pr, su, d = tiny
@@ -356,3 +444,33 @@ def test_mutation_transposed_basis_axes_is_caught(monkeypatch, tiny):
     tr = tumor.forward(su, pr.p)
     cs = dense.forward(pr.m, pr.centres, pr.sigma, pr.p, pr.rho_f, pr.k_f, pr.nt)
     assert rel(tr.c[-1], cs[-1]) > 1e-3
+
+
+def test_mutation_reaction_on_diffusion_field_is_caught(monkeypatch, tiny_full):
+    """Using the diffusion field in the reaction (forgetting m_rho) breaks
+    the dense match of the full model."""
+    pr, su, _, _, _ = tiny_full
+    bad = tumor.Setup(su.m, su.centres, su.sigma, su.rho_f, su.k_f, su.nt, rtol=su.rtol,
+                      phi_mask=su.phi_mask)
+    tr = tumor.forward(bad, pr.p)
+    cs = dense.forward(su.m, pr.centres, pr.sigma, pr.p, pr.rho_f, pr.k_f, pr.nt,
+                       m_rho=su.m_rho, mask=su.phi_mask)
+    assert rel(tr.c[-1], cs[-1]) > 1e-3
+
+
+def test_mutation_label_gradient_sign_is_caught(monkeypatch, tiny_full):
+    """A wrong sign of the label term in the terminal cotangent fails the
+    complex-step pin."""
+    pr, su, d, tis, pat = tiny_full
+    orig = tumor.misfit_labels
+
+    def bad(setup, cT, dd, m_lab, m_pat):
+        J, lam = orig(setup, cT, dd, m_lab, m_pat)
+        J0, lam0 = tumor.misfit(setup, cT, dd)
+        return J, lam0 - (lam - lam0)
+    monkeypatch.setattr(tumor, "misfit_labels", bad)
+    _, g, _ = tumor.gradient(su, pr.p, d, labels=(tis, pat))
+    gp, _, _ = dense.complex_step_gradient(su.m, pr.centres, pr.sigma, pr.p, pr.rho_f, pr.k_f,
+                                           pr.nt, d, m_rho=su.m_rho, mask=su.phi_mask,
+                                           labels=(tis, pat))
+    assert rel(g.g_p, gp) > 1e-3
