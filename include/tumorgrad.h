@@ -115,6 +115,21 @@ tg_status tg_plan_bind(tg_plan* plan, void* d_workspace, size_t bytes);
 tg_status tg_forward(tg_plan* plan, const double* d_p, const double* d_rho_f,
                      const double* d_k_f, const void* d_m, void* d_cT, void* stream);
 
+/* Forward solve with the full coefficient model of Sec. 2.1: diffusion
+ * k = k_f m_diff and reaction rho = rho_f m_react, where the caller forms
+ * m_diff = sum_i k_i m_i and m_react = sum_i rho_i m_i from its tissue maps
+ * (WM, GM, CSF) and weights; and c(0) = phi_mask * Phi p, the mask zeroing
+ * the Gaussians inside CSF (e.g. phi_mask = 1 - m_CSF).  All three fields
+ * are [B][n^3] in the plan's precision.  d_m_react = NULL means m_diff,
+ * d_phi_mask = NULL means no mask; tg_forward(.., d_m, ..) is this call
+ * with (d_m, NULL, NULL).  The pointers must stay valid and unchanged like
+ * d_m above: tg_vjp, tg_adjoint_misfit(_labels) and tg_hessvec_gn use the
+ * same fields (the Gauss-Newton products use the same mask for Phi v and
+ * Phi^T).  Errors: TG_ERR_ARG if d_m_diff is NULL. */
+tg_status tg_forward_fields(tg_plan* plan, const double* d_p, const double* d_rho_f,
+                            const double* d_k_f, const void* d_m_diff, const void* d_m_react,
+                            const void* d_phi_mask, void* d_cT, void* stream);
+
 /* Vector-Jacobian product of the last forward (adjoint solve, Sec. 2.1
  * optimality conditions, evaluated as in Sec. 3.1): given a Euclidean
  * cotangent lamT [B][n^3] on c(T), writes g_p = d<lamT, c(T)>/dp [B][n_p],
@@ -126,6 +141,19 @@ tg_status tg_vjp(tg_plan* plan, const void* d_lamT, double* d_gp, double* d_grho
  * gradient: tg_vjp with lamT = h^3 (c(T) - c_obs).  Writes d_J [B]. */
 tg_status tg_adjoint_misfit(tg_plan* plan, const void* d_cobs, double* d_J, double* d_gp,
                             double* d_grho, double* d_gkf, void* stream);
+
+/* Misfit with the anatomy-label term of the Sec. 2.1 objective:
+ *   J = 1/2 h^3 sum [(c - c_obs)^2 + sum_l (m_l (1 - c) - mP_l)^2],
+ * the simulated tumor c = c(T) masking the healthy labels m_l, compared
+ * with the patient labels mP_l, and its gradient: tg_vjp with
+ *   lamT = h^3 [(c - c_obs) - sum_l m_l (m_l (1 - c) - mP_l)]
+ * (the terminal condition of the adjoint with D_m included).  d_m_lab and
+ * d_m_pat hold n_labels fields per problem, [B][n_labels][n^3], in the
+ * plan's precision; n_labels = 0 is tg_adjoint_misfit.  Errors: TG_ERR_ARG
+ * (n_labels < 0, or > 0 with a NULL label pointer), TG_ERR_STATE. */
+tg_status tg_adjoint_misfit_labels(tg_plan* plan, const void* d_cobs, int n_labels,
+                                   const void* d_m_lab, const void* d_m_pat, double* d_J,
+                                   double* d_gp, double* d_grho, double* d_gkf, void* stream);
 
 /* Gauss-Newton Hessian of J with respect to p about the last forward
  * trajectory (batch must be 1): HV[d] = Phi^T J_c^T h^3 J_c Phi V[d] for

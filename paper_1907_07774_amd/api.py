@@ -123,17 +123,28 @@ class Plan:
             t.view(self.batch, self.n, self.n, self.n)
 
     # ---------------------------------------------------------------- calls
-    def forward(self, p, rho_f, k_f, m) -> torch.Tensor:
-        """c(T) for coefficients p, growth rates rho_f and k_f, WM map m."""
+    def forward(self, p, rho_f, k_f, m, m_react=None, phi_mask=None) -> torch.Tensor:
+        """c(T) for coefficients p, growth rates rho_f and k_f, diffusion
+        field m (the WM map, or sum_i k_i m_i over tissues).  m_react: the
+        reaction field sum_i rho_i m_i (default m); phi_mask: multiplies
+        Phi p, e.g. 1 - m_CSF (default none)."""
         self._bind()
         p = self._vec(p, self.batch * self.n_p, "p")
         rho = self._vec(rho_f, self.batch, "rho_f")
         kf = self._vec(k_f, self.batch, "k_f")
         m = self._field(m, "m")
+        mr = None if m_react is None else self._field(m_react, "m_react")
+        mask = None if phi_mask is None else self._field(phi_mask, "phi_mask")
         cT = torch.empty_like(m)
-        st = _lib.lib().tg_forward(self._h, _ptr(p), _ptr(rho), _ptr(kf), _ptr(m), _ptr(cT),
-                                   self._stream())
-        self._keep = (p, rho, kf, m, cT)
+        if mr is None and mask is None:
+            st = _lib.lib().tg_forward(self._h, _ptr(p), _ptr(rho), _ptr(kf), _ptr(m),
+                                       _ptr(cT), self._stream())
+        else:
+            st = _lib.lib().tg_forward_fields(self._h, _ptr(p), _ptr(rho), _ptr(kf), _ptr(m),
+                                              _ptr(mr) if mr is not None else None,
+                                              _ptr(mask) if mask is not None else None,
+                                              _ptr(cT), self._stream())
+        self._keep = (p, rho, kf, m, mr, mask, cT)
         self.generation += 1
         _lib.check(st, "tg_forward")
         return self._shape(cT)
@@ -149,18 +160,38 @@ class Plan:
                                      self._stream()), "tg_vjp")
         return self._vecs(gp, gr, gk)
 
-    def adjoint_misfit(self, c_obs):
-        """(J, g_p, g_rho, g_kf) of J = 1/2 h^3 sum (c(T) - c_obs)^2."""
+    def adjoint_misfit(self, c_obs, labels=None):
+        """(J, g_p, g_rho, g_kf) of J = 1/2 h^3 sum (c(T) - c_obs)^2; with
+        labels = (m_lab, m_pat), each [batch][L][n^3] (or [L][n^3] for one
+        problem), J adds 1/2 h^3 sum_l sum (m_l (1 - c(T)) - mP_l)^2."""
         self._bind()
         d = self._field(c_obs, "c_obs")
         J = torch.empty(self.batch, dtype=torch.float64, device=self.device)
         gp = torch.empty(self.batch * self.n_p, dtype=torch.float64, device=self.device)
         gr = torch.empty(self.batch, dtype=torch.float64, device=self.device)
         gk = torch.empty(self.batch, dtype=torch.float64, device=self.device)
-        _lib.check(_lib.lib().tg_adjoint_misfit(self._h, _ptr(d), _ptr(J), _ptr(gp), _ptr(gr),
-                                                _ptr(gk), self._stream()), "tg_adjoint_misfit")
+        if labels is None:
+            st = _lib.lib().tg_adjoint_misfit(self._h, _ptr(d), _ptr(J), _ptr(gp), _ptr(gr),
+                                              _ptr(gk), self._stream())
+        else:
+            ml, mp = (self._labels(x, name) for x, name in zip(labels, ("m_lab", "m_pat")))
+            if ml.shape != mp.shape:
+                raise ValueError("m_lab and m_pat must have the same shape")
+            st = _lib.lib().tg_adjoint_misfit_labels(
+                self._h, _ptr(d), ml.shape[1], _ptr(ml), _ptr(mp), _ptr(J), _ptr(gp),
+                _ptr(gr), _ptr(gk), self._stream())
+        _lib.check(st, "tg_adjoint_misfit")
         gp, gr, gk = self._vecs(gp, gr, gk)
         return (J[0] if self.batch == 1 else J), gp, gr, gk
+
+    def _labels(self, x, name):
+        if not isinstance(x, torch.Tensor):
+            x = torch.as_tensor(np.asarray(x), device=self.device)
+        x = x.to(device=self.device, dtype=self.dtype).contiguous()
+        n3 = self.n ** 3
+        if x.numel() % (self.batch * n3) != 0 or x.numel() == 0:
+            raise ValueError(f"{name}: expected [{self.batch}][L][{self.n}^3] values")
+        return x.view(self.batch, x.numel() // (self.batch * n3), n3)
 
     def hessvec(self, V) -> torch.Tensor:
         """Gauss-Newton Hessian products H V[d] for V of shape [ndir, n_p]."""

@@ -169,18 +169,25 @@ tg_status tg_plan_bind(tg_plan* plan, void* d_ws, size_t bytes) {
   return TG_OK;
 }
 
-tg_status tg_forward(tg_plan* plan, const double* d_p, const double* d_rho_f, const double* d_k_f,
-                     const void* d_m, void* d_cT, void* stream) {
+tg_status tg_forward_fields(tg_plan* plan, const double* d_p, const double* d_rho_f,
+                            const double* d_k_f, const void* d_m_diff, const void* d_m_react,
+                            const void* d_phi_mask, void* d_cT, void* stream) {
   if (plan == nullptr || d_p == nullptr || d_rho_f == nullptr || d_k_f == nullptr ||
-      d_m == nullptr || d_cT == nullptr)
+      d_m_diff == nullptr || d_cT == nullptr)
     return TG_ERR_ARG;
   if (!plan->solver) return TG_ERR_WORKSPACE;
   plan->last_stream = (hipStream_t)stream;
   plan->have_traj = false;
-  hipError_t e = plan->solver->forward(d_p, d_rho_f, d_k_f, d_m, d_cT, (hipStream_t)stream);
+  hipError_t e = plan->solver->forward(d_p, d_rho_f, d_k_f, d_m_diff, d_m_react, d_phi_mask,
+                                       d_cT, (hipStream_t)stream);
   if (e != hipSuccess) return TG_ERR_HIP;
   plan->have_traj = true;
   return from_bits(plan->solver->last_status());
+}
+
+tg_status tg_forward(tg_plan* plan, const double* d_p, const double* d_rho_f, const double* d_k_f,
+                     const void* d_m, void* d_cT, void* stream) {
+  return tg_forward_fields(plan, d_p, d_rho_f, d_k_f, d_m, nullptr, nullptr, d_cT, stream);
 }
 
 tg_status tg_vjp(tg_plan* plan, const void* d_lamT, double* d_gp, double* d_grho, double* d_gkf,
@@ -191,8 +198,8 @@ tg_status tg_vjp(tg_plan* plan, const void* d_lamT, double* d_gp, double* d_grho
   if (!plan->have_traj) return TG_ERR_STATE;
   if (!plan->solver) return TG_ERR_WORKSPACE;
   plan->last_stream = (hipStream_t)stream;
-  hipError_t e = plan->solver->vjp(d_lamT, nullptr, nullptr, d_gp, d_grho, d_gkf,
-                                   (hipStream_t)stream);
+  hipError_t e = plan->solver->vjp(d_lamT, nullptr, 0, nullptr, nullptr, nullptr, d_gp, d_grho,
+                                   d_gkf, (hipStream_t)stream);
   if (e != hipSuccess) return TG_ERR_HIP;
   return from_bits(plan->solver->last_status());
 }
@@ -205,7 +212,24 @@ tg_status tg_adjoint_misfit(tg_plan* plan, const void* d_cobs, double* d_J, doub
   if (!plan->have_traj) return TG_ERR_STATE;
   if (!plan->solver) return TG_ERR_WORKSPACE;
   plan->last_stream = (hipStream_t)stream;
-  hipError_t e = plan->solver->vjp(nullptr, d_cobs, d_J, d_gp, d_grho, d_gkf, (hipStream_t)stream);
+  hipError_t e = plan->solver->vjp(nullptr, d_cobs, 0, nullptr, nullptr, d_J, d_gp, d_grho,
+                                   d_gkf, (hipStream_t)stream);
+  if (e != hipSuccess) return TG_ERR_HIP;
+  return from_bits(plan->solver->last_status());
+}
+
+tg_status tg_adjoint_misfit_labels(tg_plan* plan, const void* d_cobs, int n_labels,
+                                   const void* d_m_lab, const void* d_m_pat, double* d_J,
+                                   double* d_gp, double* d_grho, double* d_gkf, void* stream) {
+  if (plan == nullptr || d_cobs == nullptr || d_J == nullptr || d_gp == nullptr ||
+      d_grho == nullptr || d_gkf == nullptr || n_labels < 0)
+    return TG_ERR_ARG;
+  if (n_labels > 0 && (d_m_lab == nullptr || d_m_pat == nullptr)) return TG_ERR_ARG;
+  if (!plan->have_traj) return TG_ERR_STATE;
+  if (!plan->solver) return TG_ERR_WORKSPACE;
+  plan->last_stream = (hipStream_t)stream;
+  hipError_t e = plan->solver->vjp(nullptr, d_cobs, n_labels, d_m_lab, d_m_pat, d_J, d_gp,
+                                   d_grho, d_gkf, (hipStream_t)stream);
   if (e != hipSuccess) return TG_ERR_HIP;
   return from_bits(plan->solver->last_status());
 }
@@ -330,9 +354,10 @@ tg_status tg_batch_capture(int nplans, tg_plan* const* plans, const tg_batch_io*
     tg_plan* p = plans[i];
     const tg_batch_io& b = io[i];
     p->solver->set_graph_budget(budgets[i], pcg_budget == 0);
-    e = p->solver->forward(b.d_p, b.d_rho_f, b.d_k_f, b.d_m, b.d_cT, st);
+    e = p->solver->forward(b.d_p, b.d_rho_f, b.d_k_f, b.d_m, nullptr, nullptr, b.d_cT, st);
     if (e == hipSuccess)
-      e = p->solver->vjp(nullptr, b.d_cobs, b.d_J, b.d_gp, b.d_grho, b.d_gkf, st);
+      e = p->solver->vjp(nullptr, b.d_cobs, 0, nullptr, nullptr, b.d_J, b.d_gp, b.d_grho,
+                         b.d_gkf, st);
     p->solver->set_graph_budget(0, false);
     p->last_stream = st;
   }

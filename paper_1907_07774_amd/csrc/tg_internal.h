@@ -70,12 +70,18 @@ struct CallStats {
 class ISolver {
  public:
   virtual ~ISolver() {}
-  // forward(p, rho, kf, m) -> c(T); pointers are device pointers with
-  // per-problem strides n_p, 1, 1, n^3, n^3.
+  // forward(p, rho, kf, m, mr, mask) -> c(T); pointers are device pointers
+  // with per-problem strides n_p, 1, 1, n^3, n^3, n^3, n^3.  m is the
+  // diffusion field, mr the reaction field (null: m), mask multiplies Phi p
+  // (null: none).
   virtual hipError_t forward(const double* p, const double* rho, const double* kf,
-                             const void* m, void* cT, hipStream_t st) = 0;
-  virtual hipError_t vjp(const void* lamT, const void* cobs, double* J, double* gp,
-                         double* grho, double* gkf, hipStream_t st) = 0;
+                             const void* m, const void* mr, const void* mask, void* cT,
+                             hipStream_t st) = 0;
+  // nlab > 0 adds the label misfit of fields mlab, mpat ([batch][nlab][n^3])
+  // to the misfit against cobs.
+  virtual hipError_t vjp(const void* lamT, const void* cobs, int nlab, const void* mlab,
+                         const void* mpat, double* J, double* gp, double* grho, double* gkf,
+                         hipStream_t st) = 0;
   virtual hipError_t hessvec(int ndir, const double* V, double* HV, hipStream_t st) = 0;
   virtual hipError_t read_stats(CallStats* out, hipStream_t st) = 0;
   // OR of the PCG status bits the host saw during the last call

@@ -1129,6 +1129,42 @@ __global__ void __launch_bounds__(256) k_misfit(const T* __restrict__ c, const T
   if (threadIdx.x == 0) part_at(part, b, 0)[blockIdx.x] = acc[0];
 }
 
+// Misfit with the anatomy labels (Sec. 2.1 objective): the tumor-masked
+// healthy labels m_l (1 - c) against the patient labels mP_l, l < nlab,
+// fields [b][l][n^3]:
+//   lam = h3 [(c - d) - sum_l m_l (m_l (1 - c) - mP_l)],
+//   partial sum of (c - d)^2 + sum_l (m_l (1 - c) - mP_l)^2.
+template <typename T, int N>
+__global__ void __launch_bounds__(256) k_misfit_labels(const T* __restrict__ c,
+                                                       const T* __restrict__ d, int nlab,
+                                                       const T* __restrict__ mlab,
+                                                       const T* __restrict__ mpat,
+                                                       T* __restrict__ lam, double h3,
+                                                       double* __restrict__ part) {
+  __shared__ double red[NSLOT * 4];
+  constexpr long long R = RP<T, N>::REAL;
+  const int b = blockIdx.y;
+  const long long off = (long long)b * R;
+  const long long loff = (long long)b * nlab * R;
+  double acc[NSLOT] = {0.0, 0.0, 0.0, 0.0};
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < R;
+       i += (long long)gridDim.x * 256) {
+    const double ci = (double)c[off + i];
+    const double r = ci - (double)d[off + i];
+    double g = r, s = r * r;
+    for (int l = 0; l < nlab; ++l) {
+      const double ml = (double)mlab[loff + l * R + i];
+      const double e = ml * (1.0 - ci) - (double)mpat[loff + l * R + i];
+      g -= ml * e;
+      s += e * e;
+    }
+    lam[off + i] = (T)(h3 * g);
+    acc[0] += s;
+  }
+  block_sums<256>(acc, 1, red);
+  if (threadIdx.x == 0) part_at(part, b, 0)[blockIdx.x] = acc[0];
+}
+
 // Gaussian factors g[b][i][a][j] = exp(-d(x_j, c_ia)^2 / (2 sigma^2)),
 // minimum-image periodic distance (Sec. 2.1 initial condition, Sec. 4.1
 // basis of standard deviation sigma).
@@ -1146,10 +1182,12 @@ __global__ void k_basis_factors(const double* __restrict__ centres, long long c_
   g[((size_t)b * n_p + i) * 3 * n + a * n + j] = exp(-d * d / (2.0 * sigma * sigma));
 }
 
-// c0 = Phi p: one workgroup per (x, y) row chunk; thread = z.
+// c0 = w Phi p (w: the CSF mask of Sec. 2.1, or none): one workgroup per
+// (x, y) row chunk; thread = z.
 template <typename T, int N>
 __global__ void __launch_bounds__(256) k_phi(const double* __restrict__ p, long long p_bs,
                                              const double* __restrict__ g, long long g_bs,
+                                             const T* __restrict__ mask, long long mask_bs,
                                              T* __restrict__ out, long long out_bs, int n_p) {
   constexpr int ROWS = 256 / N > 0 ? 256 / N : 1;
   const int b = blockIdx.y;
@@ -1163,6 +1201,7 @@ __global__ void __launch_bounds__(256) k_phi(const double* __restrict__ p, long 
     const double* gi = gb + (size_t)i * 3 * N;
     acc += p[b * p_bs + i] * gi[x] * gi[N + y] * gi[2 * N + z];
   }
+  if (mask) acc *= (double)mask[b * mask_bs + rowid * N + z];
   out[b * out_bs + rowid * N + z] = (T)acc;
 }
 
@@ -1178,6 +1217,7 @@ struct PhiT {
 template <typename T, int N>
 __global__ void __launch_bounds__(256) k_phit(const T* __restrict__ lam, long long lam_bs,
                                               const double* __restrict__ g, long long g_bs,
+                                              const T* __restrict__ mask, long long mask_bs,
                                               double* __restrict__ partphi, int n_p) {
   using P = PhiT<T, N>;
   __shared__ double red[NSLOT * 4];
@@ -1192,7 +1232,8 @@ __global__ void __launch_bounds__(256) k_phit(const T* __restrict__ lam, long lo
     for (int rr = r0; rr < P::RB; rr += P::ROWS_T) {
       const long long rowid = (long long)blockIdx.x * P::RB + rr;
       const int x = (int)(rowid / N), y = (int)(rowid % N);
-      const double l = (double)lb[rowid * N + z];
+      double l = (double)lb[rowid * N + z];
+      if (mask) l *= (double)mask[b * mask_bs + rowid * N + z];
       for (int q = 0; q < ni; ++q) {
         const double* gi = gb + (size_t)(i0 + q) * 3 * N;
         acc[q] += gi[x] * gi[N + y] * gi[2 * N + z] * l;

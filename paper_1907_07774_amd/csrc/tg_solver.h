@@ -40,7 +40,8 @@ class Solver final : public ISolver {
     ProbScalars* sc;
     double* part;
     int nb;
-    const T* m; long long m_bs;
+    const T* m; long long m_bs;     // diffusion field
+    const T* mr;                    // reaction field (stride m_bs)
     long long traj_bs;  // batch stride of stored states (0: shared trajectory)
   };
 
@@ -124,12 +125,14 @@ class Solver final : public ISolver {
 
   // ------------------------------------------------------------ forward
   hipError_t forward(const double* p, const double* rho, const double* kf, const void* m,
-                     void* cT, hipStream_t st) override {
+                     const void* mr, const void* mask, void* cT, hipStream_t st) override {
     st_ = st;
     call_status_ = 0;
     its_max_call_ = 0;
     begin_call(0);
     m_ = (const T*)m;
+    mr_ = mr ? (const T*)mr : m_;
+    mask_ = (const T*)mask;
     cT_ = (T*)cT;
     Ctx c = prim();
     stat_sc_ = c.sc;
@@ -146,7 +149,7 @@ class Solver final : public ISolver {
     TG_LAUNCH_CHECK();
     constexpr int ROWS = 256 / N > 0 ? 256 / N : 1;
     k_phi<T, N><<<dim3(N * N / ROWS, d_.batch), 256, 0, st_>>>(
-        p, d_.n_p, w_.gfac, (long long)d_.n_p * 3 * N, ck(0), REAL, d_.n_p);
+        p, d_.n_p, w_.gfac, (long long)d_.n_p * 3 * N, mask_, REAL, ck(0), REAL, d_.n_p);
     TG_LAUNCH_CHECK();
     TG_CHECK(fwd_steps(c, 0, d_.nt, /*initial=*/true));
     live_seg_ = d_.nseg - 1;
@@ -155,8 +158,9 @@ class Solver final : public ISolver {
   }
 
   // ------------------------------------------------------------ adjoint
-  hipError_t vjp(const void* lamT, const void* cobs, double* J, double* gp, double* grho,
-                 double* gkf, hipStream_t st) override {
+  hipError_t vjp(const void* lamT, const void* cobs, int nlab, const void* mlab,
+                 const void* mpat, double* J, double* gp, double* grho, double* gkf,
+                 hipStream_t st) override {
     st_ = st;
     call_status_ = 0;
     begin_call(1);
@@ -167,8 +171,12 @@ class Solver final : public ISolver {
     TG_LAUNCH_CHECK();
     const T* lt = (const T*)lamT;
     if (cobs != nullptr) {
-      k_misfit<T, N><<<dim3(RPc::NBLK, d_.batch), 256, 0, st_>>>(cT_, (const T*)cobs, lam(0),
-                                                                h3_, w_.part);
+      if (nlab > 0)
+        k_misfit_labels<T, N><<<dim3(RPc::NBLK, d_.batch), 256, 0, st_>>>(
+            cT_, (const T*)cobs, nlab, (const T*)mlab, (const T*)mpat, lam(0), h3_, w_.part);
+      else
+        k_misfit<T, N><<<dim3(RPc::NBLK, d_.batch), 256, 0, st_>>>(cT_, (const T*)cobs, lam(0),
+                                                                  h3_, w_.part);
       TG_LAUNCH_CHECK();
       k_finalize<FIN_J><<<d_.batch, 256, 0, st_>>>(w_.sc, w_.part, RPc::NBLK, 0.5 * h3_, 0, 0);
       TG_LAUNCH_CHECK();
@@ -196,8 +204,8 @@ class Solver final : public ISolver {
     TG_LAUNCH_CHECK();
     constexpr int ROWS = 256 / N > 0 ? 256 / N : 1;
     // dc0 = Phi v for each direction
-    k_phi<T, N><<<dim3(N * N / ROWS, ndir), 256, 0, st_>>>(V, d_.n_p, w_.gfac, 0, lam(0),
-                                                          REAL, d_.n_p);
+    k_phi<T, N><<<dim3(N * N / ROWS, ndir), 256, 0, st_>>>(V, d_.n_p, w_.gfac, 0, mask_, 0,
+                                                          lam(0), REAL, d_.n_p);
     TG_LAUNCH_CHECK();
     // tangent sweep, forward in time
     for (int j = 0; j < d_.nseg; ++j) {
@@ -274,7 +282,7 @@ class Solver final : public ISolver {
     c.X = sp[0]; c.R = sp[1]; c.P = sp[2];
     c.T1 = sp[3]; c.T2 = sp[4]; c.T3 = sp[5]; c.S = sp[6];
     c.sc = w_.sc; c.part = w_.part; c.nb = d_.batch;
-    c.m = m_; c.m_bs = REAL; c.traj_bs = REAL;
+    c.m = m_; c.mr = mr_; c.m_bs = REAL; c.traj_bs = REAL;
     return c;
   }
   Ctx dirs(int ndir) {
@@ -285,7 +293,7 @@ class Solver final : public ISolver {
     c.sc = w_.sc + d_.batch;
     c.part = w_.part + (size_t)d_.batch * NSLOT * MAXBLK;
     c.nb = ndir;
-    c.m = m_; c.m_bs = 0; c.traj_bs = 0;
+    c.m = m_; c.mr = mr_; c.m_bs = 0; c.traj_bs = 0;
     return c;
   }
   T* ck(int j) { return (T*)w_.ck + (size_t)j * d_.batch * REAL; }
@@ -301,7 +309,7 @@ class Solver final : public ISolver {
 
   ZArgs zargs(const Ctx& c) {
     ZArgs a{};
-    a.m = c.m; a.m_bs = c.m_bs;
+    a.m = c.mr; a.m_bs = c.m_bs;   // the z steps apply the reaction
     a.sc = c.sc; a.part = c.part;
     a.tau = tau_;
     a.out_scale = 1.0;
@@ -645,8 +653,8 @@ class Solver final : public ISolver {
   // g[b] = Phi^T lam(b)
   hipError_t phit(const Ctx& c, double* out, long long g_bs = -1) {
     if (g_bs < 0) g_bs = (long long)d_.n_p * 3 * N;
-    k_phit<T, N><<<dim3(PT::NBLK, c.nb), 256, 0, st_>>>(lam(0), REAL, w_.gfac, g_bs, w_.partphi,
-                                                        d_.n_p);
+    k_phit<T, N><<<dim3(PT::NBLK, c.nb), 256, 0, st_>>>(lam(0), REAL, w_.gfac, g_bs, mask_,
+                                                        c.m_bs, w_.partphi, d_.n_p);
     TG_LAUNCH_CHECK();
     k_phit_final<<<dim3(d_.n_p, c.nb), 256, 0, st_>>>(w_.partphi, PT::NBLK, d_.n_p, out, d_.n_p);
     TG_LAUNCH_CHECK();
@@ -656,7 +664,9 @@ class Solver final : public ISolver {
   SolverDims d_;
   Workspace w_;
   hipStream_t st_ = nullptr;
-  const T* m_ = nullptr;
+  const T* m_ = nullptr;      // diffusion field
+  const T* mr_ = nullptr;     // reaction field
+  const T* mask_ = nullptr;   // mask of Phi p (null: none)
   T* cT_ = nullptr;
   double dt_, tau_, h3_;
   std::vector<ProbScalars> hsc_;

@@ -1,0 +1,146 @@
+"""The full coefficient and misfit model on the GPU against the FP64 oracle,
+through the C-ABI (tg_forward_fields, tg_adjoint_misfit_labels).
+
+Tissue-weighted diffusion field sum_i k_i m_i and reaction field
+sum_i rho_i m_i from seeded WM/GM/CSF maps, the basis masked by 1 - m_CSF,
+and the anatomy-label misfit against another seed's tissue maps.
+Tolerances as for the white-matter-only path: FP64 1e-10 relative at PCG
+rtol 1e-13, FP32-mixed 1e-4 relative.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import tumor
+from paper_1907_07774_amd import api, inputs
+
+pytestmark = pytest.mark.gpu
+
+K_W, RHO_W = (1.0, 0.1, 0.0), (1.0, 0.3, 0.0)   # WM, GM, CSF weights
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def full_case(n, seed, nt, rho, kf, g=2):
+    pr = inputs.problem(n, g, seed, nt=nt, rho_f=rho, k_f=kf)
+    tis = inputs.tissues(n, seed)
+    pat = inputs.tissues(n, seed + 100)
+    mk, mr = tumor.coefficient_fields(tis, K_W, RHO_W)
+    mask = tumor.csf_mask(tis[2])
+    # keep c0 = w Phi p at most 1 (away from the logistic step's pole)
+    mx = (mask * tumor.phi(pr.p, pr.centres, pr.sigma, n)).max()
+    p = pr.p / max(mx, 1.0)
+    return pr, p, mk, mr, mask, tis, pat
+
+
+def oracle_setup(pr, mk, mr, mask, rtol=1e-13):
+    return tumor.Setup(mk, pr.centres, pr.sigma, pr.rho_f, pr.k_f, pr.nt, rtol=rtol,
+                       m_rho=mr, phi_mask=mask)
+
+
+def labels_arrays(tis, pat):
+    return np.stack(tis), np.stack(pat)
+
+
+@pytest.mark.parametrize("n,nt", [(16, 4), (64, 4)])
+def test_full_model_gradient_fp64(n, nt):
+    print(f"case full_model gradient fp64 n={n}", flush=True)
+    pr, p, mk, mr, mask, tis, pat = full_case(n, 5, nt, 8.0, 0.15)
+    su = oracle_setup(pr, mk, mr, mask)
+    d = inputs.threshold_mask(tumor.forward(su, inputs.perturbed_p(p, 5)).c[-1])
+    J, g, tr = tumor.gradient(su, p, d, labels=(tis, pat))
+    plan = api.Plan(n, nt, pr.centres, pr.sigma, rtol=1e-13, precision="fp64", ckpt_stride=2)
+    cT = plan.forward(p, pr.rho_f, pr.k_f, mk, m_react=mr, phi_mask=mask).cpu().numpy()
+    assert rel(cT, tr.c[-1]) < 1e-10
+    Jg, gp, gr, gk = plan.adjoint_misfit(d, labels=labels_arrays(tis, pat))
+    assert abs(float(Jg) - J) < 1e-10 * abs(J)
+    assert rel(gp.cpu().numpy(), g.g_p) < 1e-10
+    assert abs(float(gr) - g.g_rho) < 1e-10 * abs(g.g_rho)
+    assert abs(float(gk) - g.g_k) < 1e-10 * abs(g.g_k)
+
+
+def test_full_model_gradient_fp32_64():
+    print("case full_model gradient fp32 n=64", flush=True)
+    pr, p, mk, mr, mask, tis, pat = full_case(64, 6, 4, 8.0, 0.15)
+    su = oracle_setup(pr, mk, mr, mask)
+    d = inputs.threshold_mask(tumor.forward(su, inputs.perturbed_p(p, 6)).c[-1])
+    J, g, tr = tumor.gradient(su, p, d, labels=(tis, pat))
+    plan = api.Plan(64, 4, pr.centres, pr.sigma, rtol=1e-8, precision="fp32", ckpt_stride=2)
+    cT = plan.forward(p, pr.rho_f, pr.k_f, mk, m_react=mr, phi_mask=mask).cpu().numpy()
+    assert rel(cT, tr.c[-1]) < 1e-4
+    Jg, gp, gr, gk = plan.adjoint_misfit(d, labels=labels_arrays(tis, pat))
+    assert abs(float(Jg) - J) < 1e-4 * abs(J)
+    assert rel(gp.cpu().numpy(), g.g_p) < 1e-4
+    assert abs(float(gr) - g.g_rho) < 1e-4 * abs(g.g_rho)
+    assert abs(float(gk) - g.g_k) < 1e-4 * abs(g.g_k)
+
+
+def test_full_model_hessvec_fp64():
+    """Gauss-Newton products with the masked basis (Phi v and Phi^T both
+    carry the mask) against the oracle."""
+    print("case full_model hessvec fp64 n=16", flush=True)
+    pr, p, mk, mr, mask, _, _ = full_case(16, 7, 4, 6.0, 0.2)
+    su = oracle_setup(pr, mk, mr, mask)
+    tr = tumor.forward(su, p)
+    V = inputs.hvp_directions(3, p.size, 7)
+    plan = api.Plan(16, 4, pr.centres, pr.sigma, rtol=1e-13, precision="fp64", max_hvp_dirs=3)
+    plan.forward(p, pr.rho_f, pr.k_f, mk, m_react=mr, phi_mask=mask)
+    HV = plan.hessvec(V).cpu().numpy()
+    for k in range(3):
+        assert rel(HV[k], tumor.gn_hvp(su, tr, V[k])) < 1e-10
+
+
+def test_default_fields_are_the_white_matter_path_bitwise():
+    """tg_forward_fields(m, NULL, NULL), (m, m, NULL) and (m, m, ones)
+    reproduce tg_forward bit for bit, and the label misfit with no labels
+    (or all-zero label fields) reproduces tg_adjoint_misfit."""
+    print("case full_model defaults bitwise", flush=True)
+    pr = inputs.problem(32, 2, 8, nt=4, rho_f=8.0, k_f=0.15)
+    d = inputs.threshold_mask(inputs.random_field(32, 8) + 0.5)
+    for prec in ("fp64", "fp32"):
+        plan = api.Plan(32, 4, pr.centres, pr.sigma, rtol=1e-8, precision=prec)
+        ref = plan.forward(pr.p, pr.rho_f, pr.k_f, pr.m).cpu().numpy()
+        Jr, gpr, grr, gkr = (x.cpu().numpy() for x in plan.adjoint_misfit(d))
+        ones = np.ones_like(pr.m)
+        for mr, mask in ((pr.m, None), (pr.m, ones)):
+            c = plan.forward(pr.p, pr.rho_f, pr.k_f, pr.m, m_react=mr, phi_mask=mask)
+            assert np.array_equal(c.cpu().numpy(), ref), prec
+        zeros = np.zeros((2,) + pr.m.shape)
+        Jl, gpl, grl, gkl = (x.cpu().numpy() for x in plan.adjoint_misfit(d, labels=(zeros, zeros)))
+        assert Jl == Jr and np.array_equal(gpl, gpr) and grl == grr and gkl == gkr, prec
+        del plan
+        torch.cuda.empty_cache()
+
+
+def test_full_model_batch_equals_single_fp64():
+    """Two problems with different tissue maps, masks and labels in one
+    batched plan give the single-problem results."""
+    print("case full_model batch fp64 n=32", flush=True)
+    cases = [full_case(32, s, 4, 8.0, 0.12) for s in (11, 12)]
+    singles = []
+    for i, (pr, p, mk, mr, mask, tis, pat) in enumerate(cases):
+        d = inputs.threshold_mask(inputs.random_field(32, 40 + i) + 0.4)
+        plan = api.Plan(32, 4, pr.centres, pr.sigma, rtol=1e-13, precision="fp64")
+        cT = plan.forward(p, pr.rho_f, pr.k_f, mk, m_react=mr, phi_mask=mask).cpu().numpy()
+        out = plan.adjoint_misfit(d, labels=labels_arrays(tis, pat))
+        singles.append((d, cT, [np.asarray(x.cpu().numpy()) for x in out]))
+        del plan
+    cen = np.stack([c[0].centres for c in cases])
+    plan = api.Plan(32, 4, cen, cases[0][0].sigma, rtol=1e-13, precision="fp64", batch=2)
+    cT = plan.forward(np.concatenate([c[1] for c in cases]), [c[0].rho_f for c in cases],
+                      [c[0].k_f for c in cases], np.stack([c[2] for c in cases]),
+                      m_react=np.stack([c[3] for c in cases]),
+                      phi_mask=np.stack([c[4] for c in cases])).cpu().numpy()
+    ml = np.stack([np.stack(c[5]) for c in cases])
+    mp = np.stack([np.stack(c[6]) for c in cases])
+    J, gp, gr, gk = (np.asarray(x.cpu().numpy()) for x in
+                     plan.adjoint_misfit(np.stack([s[0] for s in singles]), labels=(ml, mp)))
+    for b, (_, c1, (J1, gp1, gr1, gk1)) in enumerate(singles):
+        assert rel(cT[b], c1) < 1e-12
+        assert abs(J[b] - J1) < 1e-12 * abs(J1)
+        assert rel(gp[b], gp1) < 1e-12
+        assert abs(gr[b] - gr1) < 1e-12 * abs(gr1) and abs(gk[b] - gk1) < 1e-12 * abs(gk1)
