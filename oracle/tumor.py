@@ -261,34 +261,55 @@ class Gradient:
     g_k: float
     lam0: np.ndarray     # cotangent with respect to c^0
     its: list
+    g_mdiff: np.ndarray | None = None    # d/d m(x) of the diffusion field
+    g_mreact: np.ndarray | None = None   # d/d mr(x) of the reaction field
 
 
-def vjp(setup: Setup, tr: Trajectory, lamT) -> Gradient:
+def vjp(setup: Setup, tr: Trajectory, lamT, fields=False) -> Gradient:
     """Exact transpose of the discrete forward map applied to a cotangent
     lamT on c(T) (plain Euclidean pairing).  Returns d<lamT, c(T)>/d(p,
-    rho_f, k_f) and the cotangent on c^0."""
+    rho_f, k_f) and the cotangent on c^0.
+
+    fields=True also returns the derivatives with respect to the diffusion
+    field m and the reaction field mr at every grid point: the discrete
+    counterpart of the coupling field q(x) that the registration step of the
+    Picard iteration receives (Sec. 2.2), a time integral of k_f grad c . grad(adjoint) and
+    rho_f c (1 - c) (adjoint) terms.  Per step, with mu the Crank-Nicolson
+    adjoint solution and s = a + b:
+        g_mdiff  += -dt/2 k_f sum_j (D_j mu)(D_j s)   (D_j antisymmetric)
+        g_mreact += rho_f dt/2 lam R (1 - R)          (each reaction half step)
+    so that sum_x m g_mdiff = k_f g_k and sum_x mr g_mreact = rho_f g_rho."""
     tau = 0.5 * setup.dt
     m = setup.mr
     lam = np.array(lamT, dtype=np.float64, copy=True)
     g_rho = 0.0
     g_k = 0.0
+    gmd = np.zeros_like(lam) if fields else None
+    gmr = np.zeros_like(lam) if fields else None
     its = []
     for n in range(setup.nt - 1, -1, -1):
         cn, a, b, cn1 = tr.c[n], tr.a[n], tr.b[n], tr.c[n + 1]
         # c^{n+1} = R(b)
         g_rho += float(np.sum(lam * reaction_drho(cn1, m, tau)))
+        if fields:
+            gmr += setup.rho_f * lam * reaction_drho(cn1, 1.0, tau)
         lam = lam * reaction_du(b, m, setup.rho_f, tau)
         # (I - dt/2 A) b = (I + dt/2 A) a, A symmetric
         mu, it = _cn_solve(setup, lam, lam)
         its.append(it)
         Amu = _A_m(setup, mu)
         g_k += tau * float(np.sum(Amu * (a + b)))
+        if fields:
+            gmu, gs = spectral.grad(mu), spectral.grad(a + b)
+            gmd -= tau * setup.k_f * sum(x * y for x, y in zip(gmu, gs))
         lam = mu + tau * setup.k_f * Amu
         # a = R(c^n)
         g_rho += float(np.sum(lam * reaction_drho(a, m, tau)))
+        if fields:
+            gmr += setup.rho_f * lam * reaction_drho(a, 1.0, tau)
         lam = lam * reaction_du(cn, m, setup.rho_f, tau)
     g_p = phi_t(setup.masked(lam), setup.centres, setup.sigma)
-    return Gradient(g_p, g_rho, g_k, lam, its)
+    return Gradient(g_p, g_rho, g_k, lam, its, gmd, gmr)
 
 
 def gradient(setup: Setup, p, d, labels=None):

@@ -1,5 +1,5 @@
-"""Tumor inversion driver on top of the GPU gradient (paper Sec. 3.3,
-"Adaptivity and Convergence Criteria", and Sec. 4.1, "Regularization and
+"""Tumor inversion driver on top of the GPU gradient (paper Sec. 2.3,
+"Adaptivity and Convergence Criteria", and Sec. 3.1, "Regularization and
 Nonlinear Solver Components for Tumor Inversion").
 
 Two phases invert the Gaussian coefficients p and the diffusivity k_f of the

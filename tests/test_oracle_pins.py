@@ -405,6 +405,45 @@ def test_csf_mask_reduces_to_plain_basis_and_zeroes_csf():
     assert np.all(tumor.forward(su, pr.p).c[0][csf == 1.0] == 0.0)
 
 
+# ------------------------------------------- coupling field q(x) = dJ/dm
+def test_coupling_fields_match_dense_complex_step(tiny_full):
+    """Derivatives of J (with the label misfit) with respect to the
+    diffusion field m and the reaction field mr at every grid point,
+    checked along random smooth directions and single grid points by
+    complex-step derivatives of the dense model."""
+    pr, su, d, tis, pat = tiny_full
+    tr = tumor.forward(su, pr.p)
+    _, lamT = tumor.misfit_labels(su, tr.c[-1], d, tis, pat)
+    g = tumor.vjp(su, tr, lamT, fields=True)
+    n = su.n
+    h = 1e-30
+    dirs = [inputs.random_field(n, 50), inputs.random_field(n, 51)]
+    for idx in ((1, 2, 3), (4, 4, 4), (6, 1, 5)):
+        e = np.zeros((n,) * 3)
+        e[idx] = 1.0
+        dirs.append(e)
+    kw = dict(labels=(tis, pat), mask=su.phi_mask)
+    for dm in dirs:
+        Jd = dense.objective(su.m + 1j * h * dm, pr.centres, pr.sigma, pr.p, pr.rho_f, pr.k_f,
+                             pr.nt, d, m_rho=su.m_rho, **kw)
+        want = Jd.imag / h
+        assert abs(float(np.sum(g.g_mdiff * dm)) - want) < 1e-10 * max(abs(want), 1e-12)
+        Jr = dense.objective(su.m, pr.centres, pr.sigma, pr.p, pr.rho_f, pr.k_f, pr.nt, d,
+                             m_rho=su.m_rho + 1j * h * dm, **kw)
+        want = Jr.imag / h
+        assert abs(float(np.sum(g.g_mreact * dm)) - want) < 1e-10 * max(abs(want), 1e-12)
+
+
+def test_coupling_fields_scaling_identities(small):
+    """Scaling the diffusion (reaction) field by 1 + eps scales k_f (rho_f):
+    sum_x m g_mdiff = k_f g_k and sum_x mr g_mreact = rho_f g_rho."""
+    pr, su, tr = small
+    g = tumor.vjp(su, tr, inputs.random_field(su.n, 52), fields=True)
+    assert abs(float(np.sum(su.m * g.g_mdiff)) - su.k_f * g.g_k) < 1e-12 * abs(su.k_f * g.g_k)
+    assert abs(float(np.sum(su.mr * g.g_mreact)) - su.rho_f * g.g_rho) < \
+        1e-12 * abs(su.rho_f * g.g_rho)
+
+
 # ----------------------------------------------- mutations must be caught
 def _mutant_gradient_error(monkeypatch, name, fn, tiny):
     pr, su, d = tiny
