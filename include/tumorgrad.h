@@ -137,6 +137,26 @@ tg_status tg_forward_fields(tg_plan* plan, const double* d_p, const double* d_rh
 tg_status tg_vjp(tg_plan* plan, const void* d_lamT, double* d_gp, double* d_grho,
                  double* d_gkf, void* stream);
 
+/* tg_vjp that also returns, at every grid point x, the derivatives of
+ * <lamT, c(T)> in the diffusion field and in the reaction field of the
+ * last forward (m_diff and m_react of tg_forward_fields; both m for
+ * tg_forward): the discrete counterpart of the coupling field q(x) that
+ * the registration step of the Picard iteration receives (Sec. 2.2), a
+ * time integral of gradient-of-state times gradient-of-adjoint and
+ * c (1 - c) times adjoint terms.  Exactly, per reverse step with mu the
+ * Crank-Nicolson adjoint solution and s = a + b the step's two states:
+ *   q_diff  += -dt/2 k_f sum_j (D_j mu)(D_j s),
+ *   q_react += rho_f dt/2 lam R (1 - R)   at each reaction half step,
+ * so sum_x m_diff q_diff = k_f g_kf and sum_x m_react q_react = rho_f g_rho.
+ * For tissue maps m_i with k = k_f sum_i k_i m_i and rho = rho_f sum_i
+ * rho_i m_i, dJ/dm_i = k_i q_diff + rho_i q_react.  d_q_diff, d_q_react:
+ * [B][n^3] in the plan's precision, overwritten; either may be NULL.  The
+ * diffusion part adds five transform passes per reverse step (the
+ * gradient rows of mu and of s and one z pass that multiplies them).
+ * Errors as tg_vjp. */
+tg_status tg_vjp_coupling(tg_plan* plan, const void* d_lamT, double* d_gp, double* d_grho,
+                          double* d_gkf, void* d_q_diff, void* d_q_react, void* stream);
+
 /* Misfit J = 1/2 h^3 sum (c(T) - c_obs)^2 (tumor misfit of Tab. 1) and its
  * gradient: tg_vjp with lamT = h^3 (c(T) - c_obs).  Writes d_J [B]. */
 tg_status tg_adjoint_misfit(tg_plan* plan, const void* d_cobs, double* d_J, double* d_gp,

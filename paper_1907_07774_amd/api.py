@@ -149,16 +149,24 @@ class Plan:
         _lib.check(st, "tg_forward")
         return self._shape(cT)
 
-    def vjp(self, lamT):
-        """(g_p, g_rho, g_kf) = d<lamT, c(T)>/d(p, rho_f, k_f) of the last forward."""
+    def vjp(self, lamT, coupling: bool = False):
+        """(g_p, g_rho, g_kf) = d<lamT, c(T)>/d(p, rho_f, k_f) of the last
+        forward.  coupling=True adds (q_diff, q_react): the derivatives at
+        every grid point in the diffusion and reaction fields."""
         self._bind()
         lam = self._field(lamT, "lamT")
         gp = torch.empty(self.batch * self.n_p, dtype=torch.float64, device=self.device)
         gr = torch.empty(self.batch, dtype=torch.float64, device=self.device)
         gk = torch.empty(self.batch, dtype=torch.float64, device=self.device)
-        _lib.check(_lib.lib().tg_vjp(self._h, _ptr(lam), _ptr(gp), _ptr(gr), _ptr(gk),
-                                     self._stream()), "tg_vjp")
-        return self._vecs(gp, gr, gk)
+        if not coupling:
+            _lib.check(_lib.lib().tg_vjp(self._h, _ptr(lam), _ptr(gp), _ptr(gr), _ptr(gk),
+                                         self._stream()), "tg_vjp")
+            return self._vecs(gp, gr, gk)
+        qd, qr = torch.empty_like(lam), torch.empty_like(lam)
+        _lib.check(_lib.lib().tg_vjp_coupling(self._h, _ptr(lam), _ptr(gp), _ptr(gr), _ptr(gk),
+                                              _ptr(qd), _ptr(qr), self._stream()),
+                   "tg_vjp_coupling")
+        return (*self._vecs(gp, gr, gk), self._shape(qd), self._shape(qr))
 
     def adjoint_misfit(self, c_obs, labels=None):
         """(J, g_p, g_rho, g_kf) of J = 1/2 h^3 sum (c(T) - c_obs)^2; with
@@ -281,7 +289,8 @@ class Plan:
 
 class TumorSolve(torch.autograd.Function):
     """c(T) = TumorSolve.apply(p, rho_f, k_f, m, plan); differentiable in
-    p, rho_f and k_f through the library's discrete adjoint."""
+    p, rho_f, k_f and the white-matter map m through the library's discrete
+    adjoint (m's gradient is the coupling field, q_diff + q_react)."""
 
     @staticmethod
     def forward(ctx, p, rho_f, k_f, m, plan: Plan):
@@ -299,10 +308,16 @@ class TumorSolve(torch.autograd.Function):
             p, rho, kf, m = ctx.saved_tensors
             plan.forward(p, rho, kf, m)
             ctx.gen = plan.generation
-        gp, gr, gk = plan.vjp(grad_cT.detach())
-        p, rho, kf, _ = ctx.saved_tensors
+        p, rho, kf, m = ctx.saved_tensors
+        gm = None
+        if ctx.needs_input_grad[3]:
+            # m drives both coefficients: dJ/dm = q_diff + q_react
+            gp, gr, gk, qd, qr = plan.vjp(grad_cT.detach(), coupling=True)
+            gm = (qd + qr).reshape(m.shape).to(m.dtype)
+        else:
+            gp, gr, gk = plan.vjp(grad_cT.detach())
         return (gp.view_as(p).to(p.dtype), gr.reshape(rho.shape).to(rho.dtype),
-                gk.reshape(kf.shape).to(kf.dtype), None, None)
+                gk.reshape(kf.shape).to(kf.dtype), gm, None)
 
 
 class BatchGraph:

@@ -199,7 +199,21 @@ tg_status tg_vjp(tg_plan* plan, const void* d_lamT, double* d_gp, double* d_grho
   if (!plan->solver) return TG_ERR_WORKSPACE;
   plan->last_stream = (hipStream_t)stream;
   hipError_t e = plan->solver->vjp(d_lamT, nullptr, 0, nullptr, nullptr, nullptr, d_gp, d_grho,
-                                   d_gkf, (hipStream_t)stream);
+                                   d_gkf, nullptr, nullptr, (hipStream_t)stream);
+  if (e != hipSuccess) return TG_ERR_HIP;
+  return from_bits(plan->solver->last_status());
+}
+
+tg_status tg_vjp_coupling(tg_plan* plan, const void* d_lamT, double* d_gp, double* d_grho,
+                          double* d_gkf, void* d_q_diff, void* d_q_react, void* stream) {
+  if (plan == nullptr || d_lamT == nullptr || d_gp == nullptr || d_grho == nullptr ||
+      d_gkf == nullptr)
+    return TG_ERR_ARG;
+  if (!plan->have_traj) return TG_ERR_STATE;
+  if (!plan->solver) return TG_ERR_WORKSPACE;
+  plan->last_stream = (hipStream_t)stream;
+  hipError_t e = plan->solver->vjp(d_lamT, nullptr, 0, nullptr, nullptr, nullptr, d_gp, d_grho,
+                                   d_gkf, d_q_diff, d_q_react, (hipStream_t)stream);
   if (e != hipSuccess) return TG_ERR_HIP;
   return from_bits(plan->solver->last_status());
 }
@@ -213,7 +227,7 @@ tg_status tg_adjoint_misfit(tg_plan* plan, const void* d_cobs, double* d_J, doub
   if (!plan->solver) return TG_ERR_WORKSPACE;
   plan->last_stream = (hipStream_t)stream;
   hipError_t e = plan->solver->vjp(nullptr, d_cobs, 0, nullptr, nullptr, d_J, d_gp, d_grho,
-                                   d_gkf, (hipStream_t)stream);
+                                   d_gkf, nullptr, nullptr, (hipStream_t)stream);
   if (e != hipSuccess) return TG_ERR_HIP;
   return from_bits(plan->solver->last_status());
 }
@@ -229,7 +243,7 @@ tg_status tg_adjoint_misfit_labels(tg_plan* plan, const void* d_cobs, int n_labe
   if (!plan->solver) return TG_ERR_WORKSPACE;
   plan->last_stream = (hipStream_t)stream;
   hipError_t e = plan->solver->vjp(nullptr, d_cobs, n_labels, d_m_lab, d_m_pat, d_J, d_gp,
-                                   d_grho, d_gkf, (hipStream_t)stream);
+                                   d_grho, d_gkf, nullptr, nullptr, (hipStream_t)stream);
   if (e != hipSuccess) return TG_ERR_HIP;
   return from_bits(plan->solver->last_status());
 }
@@ -357,7 +371,7 @@ tg_status tg_batch_capture(int nplans, tg_plan* const* plans, const tg_batch_io*
     e = p->solver->forward(b.d_p, b.d_rho_f, b.d_k_f, b.d_m, nullptr, nullptr, b.d_cT, st);
     if (e == hipSuccess)
       e = p->solver->vjp(nullptr, b.d_cobs, 0, nullptr, nullptr, b.d_J, b.d_gp, b.d_grho,
-                         b.d_gkf, st);
+                         b.d_gkf, nullptr, nullptr, st);
     p->solver->set_graph_budget(0, false);
     p->last_stream = st;
   }

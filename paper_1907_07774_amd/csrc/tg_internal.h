@@ -78,10 +78,11 @@ class ISolver {
                              const void* m, const void* mr, const void* mask, void* cT,
                              hipStream_t st) = 0;
   // nlab > 0 adds the label misfit of fields mlab, mpat ([batch][nlab][n^3])
-  // to the misfit against cobs.
+  // to the misfit against cobs.  qk, qr (null: skip) receive the per-voxel
+  // derivatives in the diffusion and reaction fields ([batch][n^3]).
   virtual hipError_t vjp(const void* lamT, const void* cobs, int nlab, const void* mlab,
                          const void* mpat, double* J, double* gp, double* grho, double* gkf,
-                         hipStream_t st) = 0;
+                         void* qk, void* qr, hipStream_t st) = 0;
   virtual hipError_t hessvec(int ndir, const double* V, double* HV, hipStream_t st) = 0;
   virtual hipError_t read_stats(CallStats* out, hipStream_t st) = 0;
   // OR of the PCG status bits the host saw during the last call

@@ -757,6 +757,7 @@ struct ZArgs {
   void* Y2;                            // second spectral output (adjoint)
   ProbScalars* sc;
   double* part;
+  void* Qr;                            // adjoint: += d J / d mr(x) (null: skip)
   double tau;
   double out_scale;                    // factor on the stored tangent output
   int want_grho;
@@ -789,10 +790,16 @@ __global__ void __launch_bounds__((ZP<T, N, RW>::NT)) k_z_step(ZArgs a) {
     for (int e = 0; e < E; ++e) r[t + TT * e] = o[e];
   };
   double gr = 0.0;
-  // d rho contribution <lam, m tau u (1 - u)> for one pair
-  auto drho = [&](cx<T> lam, cx<T> u, cx<T> mm) -> double {
-    return (double)lam.x * (double)(mm.x * tau * u.x * (T(1) - u.x)) +
-           (double)lam.y * (double)(mm.y * tau * u.y * (T(1) - u.y));
+  // d rho contribution <lam, m tau u (1 - u)> for one pair; with Qr the
+  // per-voxel lam u (1 - u) is also kept (times rho_f tau at the end: the
+  // derivative in the reaction field mr at that voxel)
+  cx<T> qv[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) qv[e] = mk(T(0), T(0));
+  auto drho = [&](cx<T> lam, cx<T> u, cx<T> mm, cx<T>& q) -> double {
+    const cx<T> w = mk(u.x * (T(1) - u.x), u.y * (T(1) - u.y));
+    q = mk(q.x + lam.x * w.x, q.y + lam.y * w.y);
+    return (double)lam.x * (double)(mm.x * tau * w.x) + (double)lam.y * (double)(mm.y * tau * w.y);
   };
   if constexpr (MODE == ZS_FWD_FIRST) {
     ldreal(a.Cin, a.cin_bs, v);
@@ -867,7 +874,7 @@ __global__ void __launch_bounds__((ZP<T, N, RW>::NT)) k_z_step(ZArgs a) {
       for (int e = 0; e < E; ++e) {
         const cx<T> c1 = mk(react(bb[e].x, E2[e].x), react(bb[e].y, E2[e].y));
         const cx<T> a1 = mk(react(c1.x, E2[e].x), react(c1.y, E2[e].y));
-        gr += drho(v[e], a1, mv[e]);
+        gr += drho(v[e], a1, mv[e], qv[e]);
         v[e] = mk(react_du(c1.x, E2[e].x) * v[e].x, react_du(c1.y, E2[e].y) * v[e].y);
       }
     }
@@ -877,7 +884,7 @@ __global__ void __launch_bounds__((ZP<T, N, RW>::NT)) k_z_step(ZArgs a) {
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const cx<T> a0 = mk(react(cc[e].x, E2[e].x), react(cc[e].y, E2[e].y));
-        gr += drho(v[e], a0, mv[e]);
+        gr += drho(v[e], a0, mv[e], qv[e]);
         v[e] = mk(react_du(cc[e].x, E2[e].x) * v[e].x, react_du(cc[e].y, E2[e].y) * v[e].y);
       }
       streal(a.Cst, a.cst_bs, v);
@@ -886,7 +893,7 @@ __global__ void __launch_bounds__((ZP<T, N, RW>::NT)) k_z_step(ZArgs a) {
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const cx<T> c1 = mk(react(bb[e].x, E2[e].x), react(bb[e].y, E2[e].y));
-        gr += drho(v[e], c1, mv[e]);
+        gr += drho(v[e], c1, mv[e], qv[e]);
         v[e] = mk(react_du(bb[e].x, E2[e].x) * v[e].x, react_du(bb[e].y, E2[e].y) * v[e].y);
       }
       r2c_row<T, N>(v, lds, t, row);
@@ -902,12 +909,73 @@ __global__ void __launch_bounds__((ZP<T, N, RW>::NT)) k_z_step(ZArgs a) {
 #pragma unroll
       for (int e = 0; e < E; ++e) Y2[t + TT * e] = v[e];
     }
+    if (a.Qr) {
+      const T qs = rhof * tau;
+      cx<T>* q = reinterpret_cast<cx<T>*>((T*)a.Qr + b * Z::REAL + roff);
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const cx<T> o = q[t + TT * e];
+        q[t + TT * e] = mk(o.x + qs * qv[e].x, o.y + qs * qv[e].y);
+      }
+    }
     if (a.want_grho) {
       double acc[NSLOT] = {gr, 0.0, 0.0, 0.0};
       block_sums<Z::NT>(acc, 1, red);
       if (threadIdx.x == 0) part_at(a.part, b, 0)[blockIdx.x] = acc[0];
     }
   }
+}
+
+// ---- per-voxel derivative in the diffusion field of one adjoint step:
+// Qk(x) += -tau k_f sum_j (D_j mu)(x) (D_j s)(x), from the y-inverted
+// gradient rows of mu (M1, M2, M3) and of s = a + b (S1, S2, S3) as the
+// matvec's y pass leaves them (row 3 still needs i wz before the z
+// transform).  One pass over six spectral rows and the real output row.
+template <typename T, int N, int RW>
+__global__ void __launch_bounds__((ZP<T, N, RW>::NT)) k_z_qgrad(
+    const cx<T>* __restrict__ M1, const cx<T>* __restrict__ M2, const cx<T>* __restrict__ M3,
+    const cx<T>* __restrict__ S1, const cx<T>* __restrict__ S2, const cx<T>* __restrict__ S3,
+    T* __restrict__ Qk, const ProbScalars* __restrict__ sc, double tau) {
+  ZP_SETUP
+  const cx<T>* Ms[3] = {M1 + sbase, M2 + sbase, M3 + sbase};
+  const cx<T>* Ss[3] = {S1 + sbase, S2 + sbase, S3 + sbase};
+  cx<T> acc[E], u[E], w[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) acc[e] = mk(T(0), T(0));
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      u[e] = Ms[j][t + TT * e];
+      w[e] = Ss[j][t + TT * e];
+    }
+    if (j == 2) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const T kz = (T)(t + TT * e);  // slot 0 (kz = 0 and n/2) has no z derivative
+        u[e] = mul_i(u[e], kz);
+        w[e] = mul_i(w[e], kz);
+      }
+    }
+    c2r_row<T, N>(u, lds, t, row);
+    c2r_row<T, N>(w, lds, t, row);
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] = mk(acc[e].x + u[e].x * w[e].x, acc[e].y + u[e].y * w[e].y);
+  }
+  const T cs = (T)(-tau * sc[b].kf);
+  cx<T>* q = reinterpret_cast<cx<T>*>(Qk + b * Z::REAL + grow * N);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const cx<T> o = q[t + TT * e];
+    q[t + TT * e] = mk(o.x + cs * acc[e].x, o.y + cs * acc[e].y);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_zero(T* __restrict__ dst, long long n) {
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (long long)gridDim.x * 256)
+    dst[i] = T(0);
 }
 
 // ---------------------------------------------------------- finalizers

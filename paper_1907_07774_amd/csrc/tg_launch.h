@@ -40,6 +40,9 @@ struct Sched {
                    const ProbScalars* sc, double* part, int pred, int rev, int nb, int k,
                    int nslab, hipStream_t st) = nullptr;
   void (*z_step)(int mode, const ZArgs& a, int nb, hipStream_t st) = nullptr;
+  void (*z_qgrad)(const cx<T>* M1, const cx<T>* M2, const cx<T>* M3, const cx<T>* S1,
+                  const cx<T>* S2, const cx<T>* S3, T* Qk, const ProbScalars* sc, double tau,
+                  int nb, hipStream_t st) = nullptr;
 };
 
 template <typename T, int N, int C, int OCC>
@@ -155,12 +158,18 @@ struct ZLaunch {
       default: zs<ZS_ADJ_LAST>(a, nb, st); break;
     }
   }
+  static void z_qgrad(const cx<T>* M1, const cx<T>* M2, const cx<T>* M3, const cx<T>* S1,
+                      const cx<T>* S2, const cx<T>* S3, T* Qk, const ProbScalars* sc,
+                      double tau, int nb, hipStream_t st) {
+    k_z_qgrad<T, N, RW><<<dim3(Z::NBLK, nb), Z::NT, 0, st>>>(M1, M2, M3, S1, S2, S3, Qk, sc, tau);
+  }
   static void fill(Sched<T, N>& s) {
     s.RW = RW;
     s.z_nblk = Z::NBLK;
     s.zm_nblk = ZM::NBLK;
     s.z_matvec = &z_matvec;
     s.z_step = &z_step;
+    s.z_qgrad = &z_qgrad;
   }
   static void fill_matvec(Sched<T, N>& s) {
     s.zm_nblk = ZM::NBLK;

@@ -159,8 +159,8 @@ class Solver final : public ISolver {
 
   // ------------------------------------------------------------ adjoint
   hipError_t vjp(const void* lamT, const void* cobs, int nlab, const void* mlab,
-                 const void* mpat, double* J, double* gp, double* grho, double* gkf,
-                 hipStream_t st) override {
+                 const void* mpat, double* J, double* gp, double* grho, double* gkf, void* qk,
+                 void* qr, hipStream_t st) override {
     st_ = st;
     call_status_ = 0;
     begin_call(1);
@@ -169,6 +169,14 @@ class Solver final : public ISolver {
     stat_nb_ = c.nb;
     k_reset_call<<<(d_.batch + 63) / 64, 64, 0, st_>>>(w_.sc, d_.batch);
     TG_LAUNCH_CHECK();
+    qk_ = (T*)qk;
+    qr_ = (T*)qr;
+    for (T* q : {qk_, qr_}) {
+      if (q == nullptr) continue;
+      const long long nq = (long long)d_.batch * REAL;
+      k_zero<T><<<(int)std::min<long long>((nq + 255) / 256, 8192), 256, 0, st_>>>(q, nq);
+      TG_LAUNCH_CHECK();
+    }
     const T* lt = (const T*)lamT;
     if (cobs != nullptr) {
       if (nlab > 0)
@@ -182,7 +190,9 @@ class Solver final : public ISolver {
       TG_LAUNCH_CHECK();
       lt = lam(0);
     }
-    TG_CHECK(adjoint_sweep(c, lt, REAL, /*gn=*/false));
+    const hipError_t ea = adjoint_sweep(c, lt, REAL, /*gn=*/false);
+    qk_ = qr_ = nullptr;
+    TG_CHECK(ea);
     TG_CHECK(phit(c, gp));
     k_emit_grads<<<(d_.batch + 63) / 64, 64, 0, st_>>>(w_.sc, cobs ? J : nullptr, grho, gkf,
                                                        d_.batch);
@@ -600,6 +610,7 @@ class Solver final : public ISolver {
       for (int n = n1 - 1; n >= n0; --n) {
         ZArgs a = zargs(c);
         a.want_grho = gn ? 0 : 1;
+        if (!gn) a.Qr = qr_;
         a.Bn = bn_ptr(n); a.bn_bs = c.traj_bs;
         a.Cn = cn_ptr(n); a.cn_bs = c.traj_bs;
         if (n == d_.nt - 1) {
@@ -616,6 +627,7 @@ class Solver final : public ISolver {
           TG_LAUNCH_CHECK();
         }
         TG_CHECK(step_solve(c, true));
+        if (!gn && qk_ != nullptr) TG_CHECK(coupling_diffusion(c));
         // lam_a = mu + tau k_f A_m mu; g_k += tau <A_m mu, a + b>
         sch_.x_inv_grad(0, c.X, nullptr, c.T1, c.T2, c.sc, nullptr, tau_, 0, c.nb, st_);
         matvec_mid(c, c.T1, c.T2, c.T3, 0);
@@ -632,6 +644,7 @@ class Solver final : public ISolver {
     TG_CHECK(inv_xy(c, c.X, c.T1));
     ZArgs a = zargs(c);
     a.want_grho = gn ? 0 : 1;
+    if (!gn) a.Qr = qr_;
     a.Xs = c.T1;
     a.Cn = ck(0); a.cn_bs = c.traj_bs;
     a.Cst = lam(0); a.cst_bs = REAL;
@@ -641,6 +654,22 @@ class Solver final : public ISolver {
       k_finalize<FIN_GRHO><<<c.nb, 256, 0, st_>>>(c.sc, c.part, sch_.z_nblk, 1.0, 0, 0);
       TG_LAUNCH_CHECK();
     }
+    return hipSuccess;
+  }
+
+  // Per-voxel derivative in the diffusion field for one reverse step, after
+  // its solve left mu in X and s = a + b in S (both spectral, kept for the
+  // k_f gradient that follows): the gradient rows of s (into R, P and the
+  // real cotangent buffer, free during the sweep) and of mu (T1..T3), then
+  // one z pass that forms -tau k_f sum_j D_j mu D_j s into qk.
+  hipError_t coupling_diffusion(const Ctx& c) {
+    cx<T>* Q8 = (cx<T>*)w_.lam;   // n^3 reals = one packed half spectrum
+    sch_.x_inv_grad(0, c.S, nullptr, c.R, c.P, c.sc, nullptr, tau_, 0, c.nb, st_);
+    sch_.y_inv_grad(c.R, c.P, Q8, c.sc, 0, c.nb, 0, 1, st_);
+    sch_.x_inv_grad(0, c.X, nullptr, c.T1, c.T2, c.sc, nullptr, tau_, 0, c.nb, st_);
+    sch_.y_inv_grad(c.T1, c.T2, c.T3, c.sc, 0, c.nb, 0, 1, st_);
+    sch_.z_qgrad(c.T1, c.T2, c.T3, c.R, c.P, Q8, qk_, c.sc, tau_, c.nb, st_);
+    TG_LAUNCH_CHECK();
     return hipSuccess;
   }
 
@@ -667,6 +696,8 @@ class Solver final : public ISolver {
   const T* m_ = nullptr;      // diffusion field
   const T* mr_ = nullptr;     // reaction field
   const T* mask_ = nullptr;   // mask of Phi p (null: none)
+  T* qk_ = nullptr;           // vjp outputs d J / d m(x), d J / d mr(x)
+  T* qr_ = nullptr;
   T* cT_ = nullptr;
   double dt_, tau_, h3_;
   std::vector<ProbScalars> hsc_;

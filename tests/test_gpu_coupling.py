@@ -1,0 +1,152 @@
+"""Per-voxel derivatives in the diffusion and reaction fields (the coupling
+field q(x) of the Picard registration step) on the GPU against the FP64
+oracle, through tg_vjp_coupling.
+
+FP64 1e-10 relative L2 at PCG rtol 1e-13; FP32-mixed 1e-4.  At the
+256^3 benchmark size, where the oracle is too slow, the scaling
+identities sum_x m q_diff = k_f g_kf and sum_x mr q_react = rho_f g_rho
+hold for the GPU's own outputs.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import tumor
+from paper_1907_07774_amd import api, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def wm_case(n, seed, nt, rho, kf):
+    pr = inputs.problem(n, 2, seed, nt=nt, rho_f=rho, k_f=kf)
+    mx = tumor.phi(pr.p, pr.centres, pr.sigma, n).max()
+    return pr, pr.p / max(mx, 1.0)
+
+
+@pytest.mark.parametrize("n,nt,ckpt", [(16, 4, 0), (64, 4, 2)])
+def test_coupling_fields_fp64(n, nt, ckpt):
+    """White-matter model; with checkpoints the reverse sweep recomputes a
+    segment in between, which reuses the buffer the diffusion part borrows."""
+    print(f"case coupling fp64 n={n} ckpt={ckpt}", flush=True)
+    pr, p = wm_case(n, 21, nt, 8.0, 0.15)
+    su = tumor.Setup(pr.m, pr.centres, pr.sigma, pr.rho_f, pr.k_f, nt, rtol=1e-13)
+    tr = tumor.forward(su, p)
+    lam = inputs.random_field(n, 21)
+    g = tumor.vjp(su, tr, lam, fields=True)
+    plan = api.Plan(n, nt, pr.centres, pr.sigma, rtol=1e-13, precision="fp64", ckpt_stride=ckpt)
+    plan.forward(p, pr.rho_f, pr.k_f, pr.m)
+    gp, gr, gk, qd, qr = plan.vjp(lam, coupling=True)
+    assert rel(qd.cpu().numpy(), g.g_mdiff) < 1e-10
+    assert rel(qr.cpu().numpy(), g.g_mreact) < 1e-10
+    assert rel(gp.cpu().numpy(), g.g_p) < 1e-10
+    assert abs(float(gr) - g.g_rho) < 1e-10 * abs(g.g_rho)
+    assert abs(float(gk) - g.g_k) < 1e-10 * abs(g.g_k)
+    # the plain vjp after it is unchanged (the coupling outputs are off again)
+    gp2, gr2, gk2 = plan.vjp(lam)
+    assert np.array_equal(gp2.cpu().numpy(), gp.cpu().numpy()) and float(gk2) == float(gk)
+
+
+def test_coupling_fields_full_model_fp64():
+    """Separate diffusion and reaction fields, masked basis, cotangent of
+    the misfit with anatomy labels."""
+    print("case coupling full model fp64 n=32", flush=True)
+    n, nt = 32, 4
+    pr = inputs.problem(n, 2, 22, nt=nt, rho_f=8.0, k_f=0.12)
+    tis, pat = inputs.tissues(n, 22), inputs.tissues(n, 122)
+    mk, mr = tumor.coefficient_fields(tis, (1.0, 0.1, 0.0), (1.0, 0.3, 0.0))
+    mask = tumor.csf_mask(tis[2])
+    p = pr.p / max((mask * tumor.phi(pr.p, pr.centres, pr.sigma, n)).max(), 1.0)
+    su = tumor.Setup(mk, pr.centres, pr.sigma, pr.rho_f, pr.k_f, nt, rtol=1e-13, m_rho=mr,
+                     phi_mask=mask)
+    tr = tumor.forward(su, p)
+    d = inputs.threshold_mask(tumor.forward(su, inputs.perturbed_p(p, 22)).c[-1])
+    _, lamT = tumor.misfit_labels(su, tr.c[-1], d, tis, pat)
+    g = tumor.vjp(su, tr, lamT, fields=True)
+    plan = api.Plan(n, nt, pr.centres, pr.sigma, rtol=1e-13, precision="fp64", ckpt_stride=2)
+    plan.forward(p, pr.rho_f, pr.k_f, mk, m_react=mr, phi_mask=mask)
+    _, _, _, qd, qr = plan.vjp(lamT, coupling=True)
+    assert rel(qd.cpu().numpy(), g.g_mdiff) < 1e-10
+    assert rel(qr.cpu().numpy(), g.g_mreact) < 1e-10
+
+
+def test_coupling_fields_fp32_64():
+    print("case coupling fp32 n=64", flush=True)
+    pr, p = wm_case(64, 23, 4, 8.0, 0.15)
+    su = tumor.Setup(pr.m, pr.centres, pr.sigma, pr.rho_f, pr.k_f, 4, rtol=1e-13)
+    tr = tumor.forward(su, p)
+    lam = inputs.random_field(64, 23)
+    g = tumor.vjp(su, tr, lam, fields=True)
+    plan = api.Plan(64, 4, pr.centres, pr.sigma, rtol=1e-8, precision="fp32", ckpt_stride=2)
+    plan.forward(p, pr.rho_f, pr.k_f, pr.m)
+    _, _, _, qd, qr = plan.vjp(lam, coupling=True)
+    assert rel(qd.cpu().numpy(), g.g_mdiff) < 1e-4
+    assert rel(qr.cpu().numpy(), g.g_mreact) < 1e-4
+
+
+def test_autograd_gradient_in_m_fp64():
+    """TumorSolve is differentiable in the white-matter map: m.grad is the
+    sum of the two coupling fields (m drives both coefficients)."""
+    print("case coupling autograd m fp64 n=16", flush=True)
+    pr, p = wm_case(16, 24, 4, 6.0, 0.2)
+    su = tumor.Setup(pr.m, pr.centres, pr.sigma, pr.rho_f, pr.k_f, 4, rtol=1e-13)
+    tr = tumor.forward(su, p)
+    lam = inputs.random_field(16, 24)
+    g = tumor.vjp(su, tr, lam, fields=True)
+    plan = api.Plan(16, 4, pr.centres, pr.sigma, rtol=1e-13, precision="fp64")
+    dev = torch.device("cuda:0")
+    pt = torch.tensor(p, device=dev, requires_grad=True)
+    rt = torch.tensor([pr.rho_f], dtype=torch.float64, device=dev, requires_grad=True)
+    kt = torch.tensor([pr.k_f], dtype=torch.float64, device=dev, requires_grad=True)
+    mt = torch.tensor(pr.m, device=dev, requires_grad=True)
+    cT = api.TumorSolve.apply(pt, rt, kt, mt, plan)
+    (cT * torch.tensor(lam, device=dev)).sum().backward()
+    assert rel(mt.grad.cpu().numpy(), g.g_mdiff + g.g_mreact) < 1e-10
+    assert rel(pt.grad.cpu().numpy(), g.g_p) < 1e-10
+
+
+def test_coupling_batch_equals_single_fp64():
+    print("case coupling batch fp64 n=32", flush=True)
+    cases = [wm_case(32, s, 4, 8.0, 0.12) for s in (25, 26)]
+    lams = [inputs.random_field(32, 60 + i) for i in range(2)]
+    singles = []
+    for (pr, p), lam in zip(cases, lams):
+        plan = api.Plan(32, 4, pr.centres, pr.sigma, rtol=1e-13, precision="fp64")
+        plan.forward(p, pr.rho_f, pr.k_f, pr.m)
+        _, _, _, qd, qr = plan.vjp(lam, coupling=True)
+        singles.append((qd.cpu().numpy(), qr.cpu().numpy()))
+        del plan
+    cen = np.stack([c[0].centres for c in cases])
+    plan = api.Plan(32, 4, cen, cases[0][0].sigma, rtol=1e-13, precision="fp64", batch=2)
+    plan.forward(np.concatenate([c[1] for c in cases]), [c[0].rho_f for c in cases],
+                 [c[0].k_f for c in cases], np.stack([c[0].m for c in cases]))
+    _, _, _, qd, qr = plan.vjp(np.stack(lams), coupling=True)
+    for b, (qd1, qr1) in enumerate(singles):
+        assert rel(qd[b].cpu().numpy(), qd1) < 1e-12
+        assert rel(qr[b].cpu().numpy(), qr1) < 1e-12
+
+
+def test_coupling_identities_256_fp32():
+    """Benchmark workload (256^3, nt = 32, checkpoint stride 4, FP32-mixed):
+    the coupling fields integrate to the scalar gradients."""
+    print("case coupling identities 256 fp32", flush=True)
+    pr = inputs.problem(256, 4, 0, nt=32)
+    plan = api.Plan(256, 32, pr.centres, pr.sigma, rtol=1e-8, precision="fp32", ckpt_stride=4)
+    m = torch.tensor(pr.m, dtype=torch.float32, device="cuda:0")
+    cT = plan.forward(pr.p, pr.rho_f, pr.k_f, m)
+    d = (cT > 0.5).float()
+    lam = (cT - d) * float((2 * np.pi / 256) ** 3)
+    _, gr, gk, qd, qr = plan.vjp(lam, coupling=True)
+    assert plan.stats().status_bits == 0
+    md = m.double()
+    sd = float((md * qd.double()).sum())
+    sr = float((md * qr.double()).sum())
+    assert abs(sd - pr.k_f * float(gk)) < 1e-4 * abs(pr.k_f * float(gk))
+    assert abs(sr - pr.rho_f * float(gr)) < 1e-4 * abs(pr.rho_f * float(gr))
+    del plan
+    torch.cuda.empty_cache()
