@@ -53,6 +53,8 @@ def parse():
                     help="also run a plain device copy of this size (counter calibration)")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-hvp", action="store_true")
+    ap.add_argument("--no-coupling", action="store_true",
+                    help="skip the coupling-field adjoint leg")
     ap.add_argument("--batch-reps", type=int, default=3)
     return ap.parse_args()
 
@@ -334,6 +336,42 @@ def hvp_workload(torch, api, inputs, pr, args):
             "symmetry_rel_err": sym, "status_bits": st.status_bits}
 
 
+def coupling_workload(torch, np, api, pr, c_obs, args):
+    """The coupling-field adjoint (per-voxel derivatives in the diffusion and
+    reaction fields) beside the plain adjoint, same 256^3 FP32-mixed
+    trajectory and cotangent h^3 (c(T) - c_obs): seconds per adjoint sweep
+    each (median of 3), so the ratio is the cost of q(x)."""
+    dev = torch.device("cuda:0")
+    plan = api.Plan(pr.n, pr.nt, pr.centres, pr.sigma, T=pr.T, rtol=args.rtol,
+                    ckpt_stride=args.ckpt, precision="fp32")
+    m = torch.tensor(pr.m, dtype=torch.float32, device=dev)
+    cT = plan.forward(pr.p, pr.rho_f, pr.k_f, m)
+    lam = ((cT - c_obs.view_as(cT).float()) * float((2 * np.pi / pr.n) ** 3)).contiguous()
+    times = {}
+    for key, cpl in (("plain", False), ("coupling", True)):
+        ts = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = plan.vjp(lam, coupling=cpl)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        times[key] = sorted(ts)[1]
+    _, gr, gk, qd, qr = out
+    md = m.double()
+    res = {"workload": "adjoint sweep of the 256^3 FP32-mixed benchmark trajectory, with and "
+                       "without the per-voxel derivatives in the diffusion and reaction fields",
+           "seconds_plain": times["plain"], "seconds_coupling": times["coupling"],
+           "overhead": times["coupling"] / times["plain"] - 1.0,
+           "identity_rel_err_diff": abs(float((md * qd.double()).sum()) - pr.k_f * float(gk))
+           / abs(pr.k_f * float(gk)),
+           "identity_rel_err_react": abs(float((md * qr.double()).sum()) - pr.rho_f * float(gr))
+           / abs(pr.rho_f * float(gr))}
+    del plan, qd, qr
+    torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(pr, res32):
     """Time the FP64 oracle's per-iteration work at the same size (operator
     and preconditioner applications), scaled by the PCG work of one
@@ -497,6 +535,8 @@ def main():
         out["batch"] = batch_workload(torch, np, api, inputs, args.batch_reps)
     if not args.no_hvp:
         out["hessvec"] = hvp_workload(torch, api, inputs, pr, args)
+    if not args.no_coupling:
+        out["coupling"] = coupling_workload(torch, np, api, pr, c_obs, args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(pr, r32)
     print(json.dumps(out), flush=True)
