@@ -14,5 +14,7 @@ Modules
             Hessian products (Sec. 2.1, Sec. 3.1, Sec. 3.3)
   dense     brute-force dense operators on tiny grids (8^3), built from
             explicit DFT matrices, used to pin ``tumor``.
+  transport semi-Lagrangian advection of the anatomy labels, its adjoint
+            and the registration body force (Sec. 2.1, Sec. 3.2, Sec. 3.3)
 """
-from . import spectral, tumor, dense  # noqa: F401
+from . import spectral, tumor, dense, transport  # noqa: F401
