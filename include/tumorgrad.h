@@ -175,6 +175,43 @@ tg_status tg_adjoint_misfit_labels(tg_plan* plan, const void* d_cobs, int n_labe
                                    const void* d_m_lab, const void* d_m_pat, double* d_J,
                                    double* d_gp, double* d_grho, double* d_gkf, void* stream);
 
+/* Registration transport (Sec. 2.1 registration advection operator and its
+ * adjoint in the optimality system; Sec. 3.3 semi-Lagrangian time
+ * stepping), on a bound plan with batch 1, in the plan's grid and
+ * precision.  n_labels label fields m0 [n_labels][n^3] are carried by a
+ * stationary velocity v [3][n^3] (physical units on [0, 2 pi)^3) over the
+ * pseudo-time [0, 1] in nt_r steps:  dm/dt + v . grad m = 0.  Each step
+ * interpolates the previous level at the foot of the characteristic
+ * (Heun's second-order step, tricubic Lagrange interpolation on the
+ * periodic grid).  d_m1 [n_labels][n^3] receives m(1) (may be NULL).
+ * d_w = div v [n^3] (the paper's w; NULL: divergence-free) is used by
+ * tg_transport_adjoint.  d_tws: caller-owned device scratch of at least
+ * tg_transport_workspace_bytes (256-byte aligned); it holds every time
+ * level for the adjoint, so it, v and w must stay unchanged until the
+ * last tg_transport_adjoint of this transport.  The transport calls use
+ * the plan's spectral scratch buffers but no tumor state: tg_vjp and
+ * tg_hessvec_gn of an earlier tg_forward stay valid.
+ * Errors: TG_ERR_ARG (batch > 1, nt_r < 1, n_labels < 1, NULL v, m0 or
+ * tws), TG_ERR_WORKSPACE (tws too small or misaligned, plan not bound). */
+tg_status tg_transport_workspace_bytes(const tg_plan* plan, int nt_r, int n_labels,
+                                       size_t* bytes);
+tg_status tg_transport(tg_plan* plan, int nt_r, int n_labels, const void* d_v, const void* d_w,
+                       const void* d_m0, void* d_m1, void* d_tws, size_t tws_bytes,
+                       void* stream);
+
+/* Adjoint of the last tg_transport (optimize-then-discretize, as the paper
+ * treats the registration, Sec. 3.2): from lam(1) = d_lam1
+ * [n_labels][n^3], solves -dlam/dt - div(lam v) = 0 backward along the
+ * characteristics of -v (the source lam w by the trapezoid rule), writes
+ * lam(0) to d_lam0 [n_labels][n^3] and the body force
+ *   b = integral_0^1 sum_l lam_l grad m_l dt   (trapezoid over the levels,
+ *       spectral gradients)
+ * to d_body [3][n^3]; for J = <lam1, m(1)> the derivative in v is -b (the
+ * registration optimality condition applies its projection).
+ * Errors: TG_ERR_ARG (NULL pointer), TG_ERR_STATE (no transport yet). */
+tg_status tg_transport_adjoint(tg_plan* plan, const void* d_lam1, void* d_lam0, void* d_body,
+                               void* stream);
+
 /* Gauss-Newton Hessian of J with respect to p about the last forward
  * trajectory (batch must be 1): HV[d] = Phi^T J_c^T h^3 J_c Phi V[d] for
  * d < ndir, V and HV [ndir][n_p].  Tangent-linear forward plus adjoint,

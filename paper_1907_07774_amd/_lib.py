@@ -28,7 +28,7 @@ EXPORTS = (
     "tg_status_string", "tg_plan_destroy", "tg_version", "tg_kernel_timer",
     "tg_kernel_timer_read", "tg_plan_set_schedule", "tg_plan_get_schedule",
     "tg_plan_set_pass", "tg_plan_get_pass", "tg_forward_fields", "tg_adjoint_misfit_labels",
-    "tg_vjp_coupling",
+    "tg_vjp_coupling", "tg_transport_workspace_bytes", "tg_transport", "tg_transport_adjoint",
     "tg_batch_capture", "tg_batch_launch", "tg_batch_destroy",
 )
 
@@ -81,6 +81,9 @@ def lib():
     L.tg_adjoint_misfit.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.tg_forward_fields.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.tg_vjp_coupling.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    L.tg_transport_workspace_bytes.argtypes = [vp, C.c_int, C.c_int, C.POINTER(sz)]
+    L.tg_transport.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp, vp, vp, sz, vp]
+    L.tg_transport_adjoint.argtypes = [vp, vp, vp, vp, vp]
     L.tg_adjoint_misfit_labels.argtypes = [vp, vp, C.c_int, vp, vp, vp, vp, vp, vp, vp]
     L.tg_hessvec_gn.argtypes = [vp, C.c_int, vp, vp, vp]
     L.tg_stats.argtypes = [vp, C.POINTER(TgSolveStats)]

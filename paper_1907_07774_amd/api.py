@@ -201,6 +201,52 @@ class Plan:
             raise ValueError(f"{name}: expected [{self.batch}][L][{self.n}^3] values")
         return x.view(self.batch, x.numel() // (self.batch * n3), n3)
 
+    # -------------------------------------------------- registration transport
+    def transport(self, v, m0, nt_r: int, w=None) -> torch.Tensor:
+        """Semi-Lagrangian transport of the label fields m0 ([L][n^3] or
+        [L, n, n, n]) by the stationary velocity v ([3][n^3]) over nt_r
+        steps; returns m(1) as [L, n, n, n].  w = div v (default 0) is
+        used by transport_adjoint.  Needs a single-problem plan."""
+        self._bind()
+        n3 = self.n ** 3
+        v = self._many(v, 3, "v")
+        m0 = self._many(m0, None, "m0")
+        L = m0.numel() // n3
+        wt = None if w is None else self._many(w, 1, "w")
+        nb = C.c_size_t()
+        _lib.check(_lib.lib().tg_transport_workspace_bytes(self._h, int(nt_r), L, C.byref(nb)),
+                   "tg_transport_workspace_bytes")
+        tws = torch.empty(nb.value + 256, dtype=torch.uint8, device=self.device)
+        off = (-tws.data_ptr()) % 256
+        m1 = torch.empty_like(m0)
+        _lib.check(_lib.lib().tg_transport(self._h, int(nt_r), L, _ptr(v), _ptr(wt), _ptr(m0),
+                                           _ptr(m1), C.c_void_p(tws.data_ptr() + off), nb.value,
+                                           self._stream()), "tg_transport")
+        self._tkeep = (v, wt, m0, tws)
+        return m1.view(L, self.n, self.n, self.n)
+
+    def transport_adjoint(self, lam1):
+        """Adjoint of the last transport from lam(1) ([L][n^3]): returns
+        (lam(0) as [L, n, n, n], body force as [3, n, n, n])."""
+        self._bind()
+        lam1 = self._many(lam1, None, "lam1")
+        L = lam1.numel() // self.n ** 3
+        lam0 = torch.empty_like(lam1)
+        body = torch.empty(3 * self.n ** 3, dtype=self.dtype, device=self.device)
+        _lib.check(_lib.lib().tg_transport_adjoint(self._h, _ptr(lam1), _ptr(lam0), _ptr(body),
+                                                   self._stream()), "tg_transport_adjoint")
+        n = self.n
+        return lam0.view(L, n, n, n), body.view(3, n, n, n)
+
+    def _many(self, x, count, name):
+        if not isinstance(x, torch.Tensor):
+            x = torch.as_tensor(np.asarray(x), device=self.device)
+        x = x.to(device=self.device, dtype=self.dtype).contiguous()
+        n3 = self.n ** 3
+        if x.numel() == 0 or x.numel() % n3 or (count is not None and x.numel() != count * n3):
+            raise ValueError(f"{name}: expected {count or 'L'} fields of {self.n}^3 values")
+        return x
+
     def hessvec(self, V) -> torch.Tensor:
         """Gauss-Newton Hessian products H V[d] for V of shape [ndir, n_p]."""
         self._bind()

@@ -23,6 +23,7 @@ struct tg_plan {
   tg::Workspace w{};
   std::unique_ptr<tg::ISolver> solver;
   bool have_traj = false;
+  bool have_transport = false;
   hipStream_t last_stream = nullptr;
 };
 
@@ -166,6 +167,7 @@ tg_status tg_plan_bind(tg_plan* plan, void* d_ws, size_t bytes) {
   plan->solver.reset(tg::make_solver(plan->d.prec == TG_FP64 ? 1 : 0, plan->dims, plan->w));
   if (!plan->solver) return TG_ERR_ARG;
   plan->have_traj = false;
+  plan->have_transport = false;
   return TG_OK;
 }
 
@@ -257,6 +259,46 @@ tg_status tg_hessvec_gn(tg_plan* plan, int ndir, const double* d_V, double* d_HV
   hipError_t e = plan->solver->hessvec(ndir, d_V, d_HV, (hipStream_t)stream);
   if (e != hipSuccess) return TG_ERR_HIP;
   return from_bits(plan->solver->last_status());
+}
+
+tg_status tg_transport_workspace_bytes(const tg_plan* plan, int nt_r, int n_labels,
+                                       size_t* bytes) {
+  if (plan == nullptr || bytes == nullptr || nt_r < 1 || n_labels < 1) return TG_ERR_ARG;
+  const size_t es = plan->d.prec == TG_FP64 ? 8 : 4;
+  const size_t n3 = (size_t)plan->d.n * plan->d.n * plan->d.n;
+  *bytes = ((size_t)(nt_r + 1) * n_labels + 6 + 2 * (size_t)n_labels) * n3 * es;
+  return TG_OK;
+}
+
+tg_status tg_transport(tg_plan* plan, int nt_r, int n_labels, const void* d_v, const void* d_w,
+                       const void* d_m0, void* d_m1, void* d_tws, size_t tws_bytes,
+                       void* stream) {
+  if (plan == nullptr || d_v == nullptr || d_m0 == nullptr || d_tws == nullptr)
+    return TG_ERR_ARG;
+  if (plan->d.batch != 1 || nt_r < 1 || n_labels < 1) return TG_ERR_ARG;
+  size_t need = 0;
+  tg_transport_workspace_bytes(plan, nt_r, n_labels, &need);
+  if (tws_bytes < need || ((uintptr_t)d_tws % ALIGN) != 0) return TG_ERR_WORKSPACE;
+  if (!plan->solver) return TG_ERR_WORKSPACE;
+  plan->last_stream = (hipStream_t)stream;
+  plan->have_transport = false;
+  hipError_t e = plan->solver->transport(nt_r, n_labels, d_v, d_w, d_m0, d_m1, d_tws,
+                                         (hipStream_t)stream);
+  if (e != hipSuccess) return TG_ERR_HIP;
+  plan->have_transport = true;
+  return TG_OK;
+}
+
+tg_status tg_transport_adjoint(tg_plan* plan, const void* d_lam1, void* d_lam0, void* d_body,
+                               void* stream) {
+  if (plan == nullptr || d_lam1 == nullptr || d_lam0 == nullptr || d_body == nullptr)
+    return TG_ERR_ARG;
+  if (!plan->have_transport) return TG_ERR_STATE;
+  if (!plan->solver) return TG_ERR_WORKSPACE;
+  plan->last_stream = (hipStream_t)stream;
+  hipError_t e = plan->solver->transport_adjoint(d_lam1, d_lam0, d_body, (hipStream_t)stream);
+  if (e != hipSuccess) return TG_ERR_HIP;
+  return TG_OK;
 }
 
 tg_status tg_stats(tg_plan* plan, tg_solve_stats* out) {

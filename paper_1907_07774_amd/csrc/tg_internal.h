@@ -84,6 +84,17 @@ class ISolver {
                          const void* mpat, double* J, double* gp, double* grho, double* gkf,
                          void* qk, void* qr, hipStream_t st) = 0;
   virtual hipError_t hessvec(int ndir, const double* V, double* HV, hipStream_t st) = 0;
+  // Registration transport (batch 1): L label fields m0 ([L][n^3]) carried
+  // by the stationary velocity v ([3][n^3]) over ntr steps of 1/ntr; m1
+  // receives the last level.  tws: [(ntr + 1) L + 6 + 2 L][n^3] reals
+  // (trajectory, the two feet, two adjoint levels).  w = div v (null: 0)
+  // is used by the adjoint.
+  virtual hipError_t transport(int ntr, int L, const void* v, const void* w, const void* m0,
+                               void* m1, void* tws, hipStream_t st) = 0;
+  // Adjoint of the last transport from lam1 ([L][n^3]) at t = 1: lam0 and the
+  // body force ([3][n^3]).
+  virtual hipError_t transport_adjoint(const void* lam1, void* lam0, void* body,
+                                       hipStream_t st) = 0;
   virtual hipError_t read_stats(CallStats* out, hipStream_t st) = 0;
   // OR of the PCG status bits the host saw during the last call
   virtual int last_status() const = 0;

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "tg_launch.h"
+#include "tg_transport.h"
 
 namespace tg {
 
@@ -249,6 +250,56 @@ class Solver final : public ISolver {
     }
     TG_CHECK(adjoint_sweep(dc, lam(0), REAL, /*gn=*/true));
     TG_CHECK(phit(dc, HV, /*g_bs=*/0));
+    return hipSuccess;
+  }
+
+  // ------------------------------------------- registration transport
+  hipError_t transport(int ntr, int L, const void* v, const void* w, const void* m0, void* m1,
+                       void* tws, hipStream_t st) override {
+    st_ = st;
+    tr_nt_ = ntr;
+    tr_L_ = L;
+    tr_w_ = (const T*)w;
+    tr_ws_ = (T*)tws;
+    const double dt = 1.0 / ntr, h = 2.0 * M_PI / N;
+    constexpr int GB = (int)((REAL + 255) / 256);
+    k_sl_foot<T, N><<<GB, 256, 0, st_>>>((const T*)v, tr_disp(0), -dt / h);
+    TG_LAUNCH_CHECK();
+    k_sl_foot<T, N><<<GB, 256, 0, st_>>>((const T*)v, tr_disp(1), dt / h);
+    TG_LAUNCH_CHECK();
+    copy_real(tr_level(0), (const T*)m0, (long long)L * REAL);
+    for (int k = 0; k < ntr; ++k) {
+      k_sl_step<T, N><<<GB, 256, 0, st_>>>(tr_level(k), tr_level(k + 1), tr_disp(0), L, nullptr,
+                                           0.0);
+      TG_LAUNCH_CHECK();
+    }
+    if (m1 != nullptr) copy_real((T*)m1, tr_level(ntr), (long long)L * REAL);
+    TG_LAUNCH_CHECK();
+    return hipSuccess;
+  }
+
+  hipError_t transport_adjoint(const void* lam1, void* lam0, void* body,
+                               hipStream_t st) override {
+    st_ = st;
+    const int ntr = tr_nt_, L = tr_L_;
+    const double dt = 1.0 / ntr;
+    constexpr int GB = (int)((REAL + 255) / 256);
+    T* bf = (T*)body;
+    k_zero<T><<<(int)std::min<long long>((3 * REAL + 255) / 256, 8192), 256, 0, st_>>>(
+        bf, 3 * REAL);
+    TG_LAUNCH_CHECK();
+    T* cur = tr_lam(0);
+    T* nxt = tr_lam(1);
+    copy_real(cur, (const T*)lam1, (long long)L * REAL);
+    TG_CHECK(body_force(tr_level(ntr), cur, L, 0.5 * dt, bf));
+    for (int k = ntr - 1; k >= 0; --k) {
+      k_sl_step<T, N><<<GB, 256, 0, st_>>>(cur, nxt, tr_disp(1), L, tr_w_, 0.5 * dt);
+      TG_LAUNCH_CHECK();
+      std::swap(cur, nxt);
+      TG_CHECK(body_force(tr_level(k), cur, L, (k == 0 ? 0.5 : 1.0) * dt, bf));
+    }
+    copy_real((T*)lam0, cur, (long long)L * REAL);
+    TG_LAUNCH_CHECK();
     return hipSuccess;
   }
 
@@ -673,6 +724,38 @@ class Solver final : public ISolver {
     return hipSuccess;
   }
 
+  // transport workspace: levels [(ntr + 1)][L][n^3], feet [2][3][n^3],
+  // adjoint levels [2][L][n^3]
+  T* tr_level(int k) { return tr_ws_ + (size_t)k * tr_L_ * REAL; }
+  T* tr_disp(int a) { return tr_level(tr_nt_ + 1) + (size_t)a * 3 * REAL; }
+  T* tr_lam(int a) { return tr_disp(2) + (size_t)a * tr_L_ * REAL; }
+
+  void copy_real(T* dst, const T* src, long long n) {
+    // n reals = n / 2 complex (n^3 is even)
+    const long long nc = n / 2;
+    const int blocks = (int)std::min<long long>((nc + 255) / 256, 8192);
+    k_copy_spec<T><<<blocks, 256, 0, st_>>>((cx<T>*)dst, (const cx<T>*)src, nc);
+  }
+
+  // b += coef sum_l lam_l grad m_l (spectral gradients through the plan's
+  // transform passes: z R2C, y and x forward with the gradient prologue,
+  // y inverse of the gradient rows, z C2R times lam)
+  hipError_t body_force(const T* m, const T* lam, int L, double coef, T* bf) {
+    using Z = ZP<T, N>;
+    Ctx c = prim();
+    for (int l = 0; l < L; ++l) {
+      k_z_r2c<T, N, Z::RW><<<dim3(Z::NBLK, 1), Z::NT, 0, st_>>>(m + (size_t)l * REAL, c.T1);
+      TG_LAUNCH_CHECK();
+      sch_.y_plain(false, c.T1, nullptr, 1, st_);
+      sch_.x_fwd_state(c.T1, c.X, c.T2, c.T3, nullptr, 1, st_);
+      sch_.y_inv_grad(c.T2, c.T3, c.T1, c.sc, 0, 1, 0, 1, st_);
+      k_z_bforce<T, N, Z::RW><<<dim3(Z::NBLK, 1), Z::NT, 0, st_>>>(
+          c.T2, c.T3, c.T1, lam + (size_t)l * REAL, bf, coef);
+      TG_LAUNCH_CHECK();
+    }
+    return hipSuccess;
+  }
+
   void copy_spec(const Ctx& c, cx<T>* dst, const cx<T>* src) {
     const long long n = (long long)c.nb * SPECN;
     const int blocks = (int)std::min<long long>((n + 255) / 256, 4096);
@@ -698,6 +781,9 @@ class Solver final : public ISolver {
   const T* mask_ = nullptr;   // mask of Phi p (null: none)
   T* qk_ = nullptr;           // vjp outputs d J / d m(x), d J / d mr(x)
   T* qr_ = nullptr;
+  int tr_nt_ = 0, tr_L_ = 0;  // last registration transport
+  const T* tr_w_ = nullptr;
+  T* tr_ws_ = nullptr;
   T* cT_ = nullptr;
   double dt_, tau_, h3_;
   std::vector<ProbScalars> hsc_;

@@ -1,0 +1,172 @@
+// Semi-Lagrangian transport of the anatomy labels (registration state),
+// its adjoint and the body force of the registration gradient (paper
+// Sec. 2.1 registration advection operator and optimality system; Sec. 3.3
+// semi-Lagrangian time stepping, spectral derivatives).
+//
+// Characteristics by Heun's step, tricubic Lagrange interpolation on the
+// periodic grid (nodes floor(p) - 1 .. floor(p) + 2 per axis, wrapped with
+// & (n - 1): n is a power of two).  Positions are in grid units; the foot
+// of the characteristic through grid point x is stored as its displacement
+// from x, three real fields.  One thread per output grid point, z fastest.
+#pragma once
+
+#include "tg_kernels.h"
+
+namespace tg {
+namespace {
+
+template <typename T>
+__device__ __forceinline__ void lagrange4(T t, T (&w)[4]) {
+  const T tm1 = t - T(1), tm2 = t - T(2), tp1 = t + T(1);
+  w[0] = -t * tm1 * tm2 * T(1.0 / 6.0);
+  w[1] = tp1 * tm1 * tm2 * T(0.5);
+  w[2] = -tp1 * t * tm2 * T(0.5);
+  w[3] = tp1 * t * tm1 * T(1.0 / 6.0);
+}
+
+// Stencil of a point: wrapped row offsets per axis and the weights.
+template <typename T, int N>
+struct Stencil {
+  int ox[4], oy[4], oz[4];
+  T wx[4], wy[4], wz[4];
+  __device__ __forceinline__ void set(T px, T py, T pz) {
+    const T fx = floor(px), fy = floor(py), fz = floor(pz);
+    lagrange4<T>(px - fx, wx);
+    lagrange4<T>(py - fy, wy);
+    lagrange4<T>(pz - fz, wz);
+    const int bx = (int)fx - 1, by = (int)fy - 1, bz = (int)fz - 1;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      ox[a] = ((bx + a) & (N - 1)) * N * N;
+      oy[a] = ((by + a) & (N - 1)) * N;
+      oz[a] = (bz + a) & (N - 1);
+    }
+  }
+  // sum of the 64 weighted samples of f (times g at the same node if given)
+  __device__ __forceinline__ T apply(const T* __restrict__ f, const T* __restrict__ g,
+                                     T gs) const {
+    T acc = T(0);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      T sa = T(0);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int o = ox[a] + oy[b];
+        T sb = T(0);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          T s = f[o + oz[c]];
+          if (g) s *= T(1) + gs * g[o + oz[c]];
+          sb += wz[c] * s;
+        }
+        sa += wy[b] * sb;
+      }
+      acc += wx[a] * sa;
+    }
+    return acc;
+  }
+};
+
+template <int N>
+__device__ __forceinline__ void grid_ijk(long long idx, int& i, int& j, int& k) {
+  i = (int)(idx / ((long long)N * N));
+  j = (int)((idx / N) % N);
+  k = (int)(idx % N);
+}
+
+// Foot of the characteristic of s v (s = +-dt/h, v in physical units):
+// X* = x + s v(x), X = x + s/2 (v(x) + v(X*)); disp = X - x (grid units).
+template <typename T, int N>
+__global__ void __launch_bounds__(256) k_sl_foot(const T* __restrict__ v, T* __restrict__ disp,
+                                                 double s_) {
+  constexpr long long R = (long long)N * N * N;
+  const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= R) return;
+  int i, j, k;
+  grid_ijk<N>(idx, i, j, k);
+  const T s = (T)s_;
+  const T vx = v[idx], vy = v[R + idx], vz = v[2 * R + idx];
+  Stencil<T, N> st;
+  st.set((T)i + s * vx, (T)j + s * vy, (T)k + s * vz);
+  const T ux = st.apply(v, nullptr, T(0));
+  const T uy = st.apply(v + R, nullptr, T(0));
+  const T uz = st.apply(v + 2 * R, nullptr, T(0));
+  disp[idx] = T(0.5) * s * (vx + ux);
+  disp[R + idx] = T(0.5) * s * (vy + uy);
+  disp[2 * R + idx] = T(0.5) * s * (vz + uz);
+}
+
+// One transport step of L fields: dst_l(x) = src_l(x + disp(x)).
+// Adjoint form (w != null): dst_l(x) = [src_l (1 + hdt w)](x + disp(x)) /
+// (1 - hdt w(x)), the trapezoid rule for the source lam div v along the
+// characteristic.
+template <typename T, int N>
+__global__ void __launch_bounds__(256) k_sl_step(const T* __restrict__ src, T* __restrict__ dst,
+                                                 const T* __restrict__ disp, int L,
+                                                 const T* __restrict__ w, double hdt_) {
+  constexpr long long R = (long long)N * N * N;
+  const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= R) return;
+  int i, j, k;
+  grid_ijk<N>(idx, i, j, k);
+  Stencil<T, N> st;
+  st.set((T)i + disp[idx], (T)j + disp[R + idx], (T)k + disp[2 * R + idx]);
+  const T hdt = (T)hdt_;
+  const T den = w ? T(1) / (T(1) - hdt * w[idx]) : T(1);
+  for (int l = 0; l < L; ++l) dst[l * R + idx] = st.apply(src + l * R, w, hdt) * den;
+}
+
+// Real row -> spectral row (the z pass of a forward transform, no other
+// work), layout as the time-step kernels write it.
+template <typename T, int N, int RW>
+__global__ void __launch_bounds__((ZP<T, N, RW>::NT)) k_z_r2c(const T* __restrict__ f,
+                                                             cx<T>* __restrict__ X) {
+  ZP_SETUP
+  const cx<T>* r = reinterpret_cast<const cx<T>*>(f + grow * N);
+  cx<T> v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = r[t + TT * e];
+  r2c_row<T, N>(v, lds, t, row);
+  cx<T>* o = X + sbase;
+#pragma unroll
+  for (int e = 0; e < E; ++e) o[t + TT * e] = v[e];
+}
+
+// Body force increment: b_j(x) += coef lam(x) (D_j m)(x) from the
+// y-inverted gradient rows of m (V3 still needs i wz before the z
+// transform), b: three real fields.
+template <typename T, int N, int RW>
+__global__ void __launch_bounds__((ZP<T, N, RW>::NT)) k_z_bforce(
+    const cx<T>* __restrict__ V1, const cx<T>* __restrict__ V2, const cx<T>* __restrict__ V3,
+    const T* __restrict__ lam, T* __restrict__ bf, double coef) {
+  ZP_SETUP
+  constexpr long long R = Z::REAL;
+  const cx<T>* Vs[3] = {V1 + sbase, V2 + sbase, V3 + sbase};
+  const cx<T>* lr = reinterpret_cast<const cx<T>*>(lam + grow * N);
+  cx<T> u[E], lv[E];
+  const T cf = (T)coef;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const cx<T> l = lr[t + TT * e];
+    lv[e] = mk(cf * l.x, cf * l.y);
+  }
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) u[e] = Vs[j][t + TT * e];
+    if (j == 2) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) u[e] = mul_i(u[e], (T)(t + TT * e));
+    }
+    c2r_row<T, N>(u, lds, t, row);
+    cx<T>* o = reinterpret_cast<cx<T>*>(bf + j * R + grow * N);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const cx<T> p = o[t + TT * e];
+      o[t + TT * e] = mk(p.x + lv[e].x * u[e].x, p.y + lv[e].y * u[e].y);
+    }
+  }
+}
+
+}  // namespace
+}  // namespace tg
