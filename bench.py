@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--no-hvp", action="store_true")
     ap.add_argument("--no-coupling", action="store_true",
                     help="skip the coupling-field adjoint leg")
+    ap.add_argument("--no-transport", action="store_true",
+                    help="skip the registration-transport leg")
     ap.add_argument("--batch-reps", type=int, default=3)
     return ap.parse_args()
 
@@ -372,6 +374,51 @@ def coupling_workload(torch, np, api, pr, c_obs, args):
     return res
 
 
+def transport_workload(torch, np, api, inputs, args):
+    """Registration transport at 256^3, FP32: the three tissue maps carried
+    by a smooth compressible velocity (up to about two cells per step) over
+    4 semi-Lagrangian steps, then the adjoint with the body force.  Seconds
+    per call (median of 3) and the algorithmic HBM bytes of the forward
+    call over its time: feet 2 x 6 fields, 4 steps x (3 + 2 x 3) fields,
+    level copies 4 x 3 fields."""
+    n, L, nt = args.n, 3, 4
+    dev = torch.device("cuda:0")
+    x = torch.arange(n, dtype=torch.float32, device=dev) * (2 * np.pi / n)
+    X, Y, Z = torch.meshgrid(x, x, x, indexing="ij")
+    amp = 2.0 * nt * (2 * np.pi / n) / 1.6          # about two cells per step at the peak
+    v = torch.stack([amp * (torch.sin(Y) + 0.3 * torch.cos(X)),
+                     amp * (torch.cos(Z) + 0.2 * torch.sin(Y)),
+                     amp * (torch.sin(X) - 0.25 * torch.cos(Z))]).contiguous()
+    w = amp * (-0.3 * torch.sin(X) + 0.2 * torch.cos(Y) + 0.25 * torch.sin(Z))   # div v
+    m0 = torch.tensor(np.stack(inputs.tissues(n, args.seed)), dtype=torch.float32, device=dev)
+    lam1 = torch.cos(X + Z).expand(L, n, n, n).contiguous()
+    plan = api.Plan(n, 2, np.zeros((1, 3)), 0.3, precision="fp32")
+
+    def timed(fn):
+        ts = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return sorted(ts)[1], out
+    t_fwd, m1 = timed(lambda: plan.transport(v, m0, nt, w=w))
+    t_adj, (lam0, body) = timed(lambda: plan.transport_adjoint(lam1))
+    S = n ** 3 * 4
+    fwd_bytes = (2 * 6 + nt * (3 + 2 * L) + 4 * L) * S
+    a = float((m1.double() * lam1.double()).sum())
+    b = float((m0.double() * lam0.double()).sum())
+    out = {"workload": f"{n}^3 FP32, 3 tissue labels, {nt} semi-Lagrangian steps, compressible "
+                       "velocity of up to about two cells per step",
+           "seconds_transport": t_fwd, "seconds_adjoint_with_body_force": t_adj,
+           "transport_algorithmic_GB_s": fwd_bytes / t_fwd / 1e9,
+           "duality_rel_gap": abs(a - b) / abs(a)}
+    del plan, v, w, m0, m1, lam0, lam1, body
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(pr, res32):
     """Time the FP64 oracle's per-iteration work at the same size (operator
     and preconditioner applications), scaled by the PCG work of one
@@ -537,6 +584,8 @@ def main():
         out["hessvec"] = hvp_workload(torch, api, inputs, pr, args)
     if not args.no_coupling:
         out["coupling"] = coupling_workload(torch, np, api, pr, c_obs, args)
+    if not args.no_transport:
+        out["transport"] = transport_workload(torch, np, api, inputs, args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(pr, r32)
     print(json.dumps(out), flush=True)
