@@ -269,8 +269,7 @@ class Solver final : public ISolver {
     TG_LAUNCH_CHECK();
     copy_real(tr_level(0), (const T*)m0, (long long)L * REAL);
     for (int k = 0; k < ntr; ++k) {
-      k_sl_step<T, N><<<GB, 256, 0, st_>>>(tr_level(k), tr_level(k + 1), tr_disp(0), L, nullptr,
-                                           0.0);
+      sl_step(tr_level(k), tr_level(k + 1), tr_disp(0), L, nullptr, 0.0);
       TG_LAUNCH_CHECK();
     }
     if (m1 != nullptr) copy_real((T*)m1, tr_level(ntr), (long long)L * REAL);
@@ -293,9 +292,17 @@ class Solver final : public ISolver {
     copy_real(cur, (const T*)lam1, (long long)L * REAL);
     TG_CHECK(body_force(tr_level(ntr), cur, L, 0.5 * dt, bf));
     for (int k = ntr - 1; k >= 0; --k) {
-      k_sl_step<T, N><<<GB, 256, 0, st_>>>(cur, nxt, tr_disp(1), L, tr_w_, 0.5 * dt);
+      if (tr_w_ != nullptr) {
+        // numerator factor (1 + dt/2 w) first, then interpolate and divide
+        k_sl_premul<T><<<(int)std::min<long long>(GB, 8192), 256, 0, st_>>>(
+            cur, nxt, tr_w_, 0.5 * dt, L, REAL);
+        TG_LAUNCH_CHECK();
+        sl_step(nxt, cur, tr_disp(1), L, tr_w_, 0.5 * dt);
+      } else {
+        sl_step(cur, nxt, tr_disp(1), L, nullptr, 0.0);
+        std::swap(cur, nxt);
+      }
       TG_LAUNCH_CHECK();
-      std::swap(cur, nxt);
       TG_CHECK(body_force(tr_level(k), cur, L, (k == 0 ? 0.5 : 1.0) * dt, bf));
     }
     copy_real((T*)lam0, cur, (long long)L * REAL);
@@ -722,6 +729,21 @@ class Solver final : public ISolver {
     sch_.z_qgrad(c.T1, c.T2, c.T3, c.R, c.P, Q8, qk_, c.sc, tau_, c.nb, st_);
     TG_LAUNCH_CHECK();
     return hipSuccess;
+  }
+
+  // one semi-Lagrangian step of L fields; w_den: divide by (1 - hdt w)
+  void sl_step(const T* src, T* dst, const T* disp, int L, const T* w_den, double hdt) {
+    if constexpr (N >= 32) {
+      using TL = SLTile<T, N, 4>;
+      k_sl_step_lds<T, N, 4><<<TL::NBLK, 256, 0, st_>>>(src, dst, disp, L, w_den, hdt);
+    } else {
+      // small grids: direct gathers (the numerator factor is already in src)
+      constexpr int GB = (int)((REAL + 255) / 256);
+      k_sl_step<T, N><<<GB, 256, 0, st_>>>(src, dst, disp, L, nullptr, 0.0);
+      if (w_den != nullptr)
+        k_sl_div<T><<<(int)std::min<long long>(GB, 8192), 256, 0, st_>>>(dst, w_den, hdt, L,
+                                                                         REAL);
+    }
   }
 
   // transport workspace: levels [(ntr + 1)][L][n^3], feet [2][3][n^3],

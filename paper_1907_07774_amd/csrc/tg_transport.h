@@ -116,6 +116,105 @@ __global__ void __launch_bounds__(256) k_sl_step(const T* __restrict__ src, T* _
   for (int l = 0; l < L; ++l) dst[l * R + idx] = st.apply(src + l * R, w, hdt) * den;
 }
 
+// The same step with the input staged in LDS: an output tile of 8 x 8 x 32
+// points (z fastest) and a halo of H cells per side hold every stencil
+// node of points displaced by up to H - 2 cells; a point whose stencil
+// leaves the tile gathers from global memory instead, so any displacement
+// is handled.  Labels one after another through the same LDS tile.  Only
+// the denominator of the adjoint form is applied here (w_den): its
+// numerator's factor (1 + hdt w) is premultiplied into src by k_sl_premul.
+template <typename T, int N, int H>
+struct SLTile {
+  static constexpr int BX = 8, BY = 8, BZ = 32;
+  static constexpr int TX = BX + 2 * H, TY = BY + 2 * H, TZ = BZ + 2 * H;
+  static constexpr int NBLK = (N / BX) * (N / BY) * (N / BZ);
+  static_assert(N % BZ == 0 && N % BX == 0, "tile must divide the grid");
+};
+
+template <typename T, int N, int H>
+__global__ void __launch_bounds__(256) k_sl_step_lds(const T* __restrict__ src,
+                                                     T* __restrict__ dst,
+                                                     const T* __restrict__ disp, int L,
+                                                     const T* __restrict__ w_den, double hdt_) {
+  using TL = SLTile<T, N, H>;
+  constexpr long long R = (long long)N * N * N;
+  __shared__ T tile[TL::TX * TL::TY * TL::TZ];
+  const int nbz = N / TL::BZ, nby = N / TL::BY;
+  const int bz = blockIdx.x % nbz, by = (blockIdx.x / nbz) % nby, bx = blockIdx.x / (nbz * nby);
+  const int x0 = bx * TL::BX - H, y0 = by * TL::BY - H, z0 = bz * TL::BZ - H;
+  const int tz = threadIdx.x & 31, tx = threadIdx.x >> 5;   // 8 x-values, y looped
+  const int gx = bx * TL::BX + tx, gz = bz * TL::BZ + tz;
+  const T hdt = (T)hdt_;
+  for (int l = 0; l < L; ++l) {
+    const T* f = src + l * R;
+    for (int q = threadIdx.x; q < TL::TX * TL::TY * TL::TZ; q += 256) {
+      const int iz = q % TL::TZ, iy = (q / TL::TZ) % TL::TY, ix = q / (TL::TZ * TL::TY);
+      tile[q] = f[(((x0 + ix) & (N - 1)) * N + ((y0 + iy) & (N - 1))) * N + ((z0 + iz) & (N - 1))];
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int yy = 0; yy < TL::BY; ++yy) {
+      const int gy = by * TL::BY + yy;
+      const long long idx = ((long long)gx * N + gy) * N + gz;
+      const T px = (T)gx + disp[idx], py = (T)gy + disp[R + idx], pz = (T)gz + disp[2 * R + idx];
+      const T fx = floor(px), fy = floor(py), fz = floor(pz);
+      const int lx = (int)fx - 1 - x0, ly = (int)fy - 1 - y0, lz = (int)fz - 1 - z0;
+      T val;
+      if (lx >= 0 && lx <= TL::TX - 4 && ly >= 0 && ly <= TL::TY - 4 && lz >= 0 &&
+          lz <= TL::TZ - 4) {
+        T wx[4], wy[4], wz[4];
+        lagrange4<T>(px - fx, wx);
+        lagrange4<T>(py - fy, wy);
+        lagrange4<T>(pz - fz, wz);
+        T acc = T(0);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          T sa = T(0);
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const T* r = tile + ((lx + a) * TL::TY + (ly + b)) * TL::TZ + lz;
+            sa += wy[b] * (wz[0] * r[0] + wz[1] * r[1] + wz[2] * r[2] + wz[3] * r[3]);
+          }
+          acc += wx[a] * sa;
+        }
+        val = acc;
+      } else {
+        Stencil<T, N> st;
+        st.set(px, py, pz);
+        val = st.apply(f, nullptr, T(0));
+      }
+      if (w_den) val /= T(1) - hdt * w_den[idx];
+      dst[l * R + idx] = val;
+    }
+    __syncthreads();
+  }
+}
+
+// dst_l = src_l (1 + hdt w), the numerator factor of the adjoint step.
+template <typename T>
+__global__ void __launch_bounds__(256) k_sl_premul(const T* __restrict__ src, T* __restrict__ dst,
+                                                   const T* __restrict__ w, double hdt_, int L,
+                                                   long long R) {
+  const T hdt = (T)hdt_;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < R;
+       i += (long long)gridDim.x * 256) {
+    const T f = T(1) + hdt * w[i];
+    for (int l = 0; l < L; ++l) dst[l * R + i] = src[l * R + i] * f;
+  }
+}
+
+// dst_l /= (1 - hdt w), the denominator of the adjoint step (small grids).
+template <typename T>
+__global__ void __launch_bounds__(256) k_sl_div(T* __restrict__ dst, const T* __restrict__ w,
+                                                double hdt_, int L, long long R) {
+  const T hdt = (T)hdt_;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < R;
+       i += (long long)gridDim.x * 256) {
+    const T d = T(1) / (T(1) - hdt * w[i]);
+    for (int l = 0; l < L; ++l) dst[l * R + i] *= d;
+  }
+}
+
 // Real row -> spectral row (the z pass of a forward transform, no other
 // work), layout as the time-step kernels write it.
 template <typename T, int N, int RW>
