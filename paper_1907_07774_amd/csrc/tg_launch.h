@@ -2,9 +2,33 @@
 // per x/y workgroup, rows per z workgroup); a plan picks one of each at run
 // time (defaults or the autotuner's choice) without recompiling.
 #pragma once
+#include <hip/hip_ext.h>
+
 #include "tg_kernels.h"
 
 namespace tg {
+
+// Kernel timer hand-off: when the solver's timer has events pending for
+// the next launch, the launch records them with the kernel's own dispatch
+// (hipExtLaunchKernelGGL) instead of separate event packets around it,
+// which would add queue gaps of several microseconds per timed launch.
+struct LaunchEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+inline LaunchEvents& pending_events() {
+  static thread_local LaunchEvents e;
+  return e;
+}
+template <typename K, typename... A>
+inline void klaunch(K kernel, dim3 grid, dim3 block, hipStream_t st, A... args) {
+  LaunchEvents& e = pending_events();
+  if (e.start != nullptr) {
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, st, e.start, e.stop, 0, args...);
+    e.start = e.stop = nullptr;
+  } else {
+    kernel<<<grid, block, 0, st>>>(args...);
+  }
+}
 
 // The four x/y passes of the PCG matvec (x_inv_grad, y_inv_grad, y_fwd_div,
 // x_fwd_div) and the z matvec can each take their own tile shape; the
@@ -54,21 +78,21 @@ struct SLaunch {
                          const ProbScalars* sc, double* part, double tau, int pred, int nb,
                          hipStream_t st) {
     if (mode == 1)
-      k_x_inv_grad<T, N, C, 1, OCC><<<dim3(SX::NBLK, nb), SX::NT, 0, st>>>(P, R, U1, U2, sc, part,
+      klaunch(k_x_inv_grad<T, N, C, 1, OCC>, dim3(SX::NBLK, nb), dim3(SX::NT), st, P, R, U1, U2, sc, part,
                                                                            tau, pred);
     else
-      k_x_inv_grad<T, N, C, 0, OCC><<<dim3(SX::NBLK, nb), SX::NT, 0, st>>>(P, R, U1, U2, sc, part,
+      klaunch(k_x_inv_grad<T, N, C, 0, OCC>, dim3(SX::NBLK, nb), dim3(SX::NT), st, P, R, U1, U2, sc, part,
                                                                            tau, pred);
   }
   static void y_inv_grad(cx<T>* U1, cx<T>* U2, cx<T>* V3, const ProbScalars* sc, int pred, int nb,
                          int k, int nslab, hipStream_t st) {
     const int nbk = SY::NBLK / nslab;
-    k_y_inv_grad<T, N, C, OCC><<<dim3(nbk, nb), SY::NT, 0, st>>>(U1, U2, V3, sc, pred, k * nbk);
+    klaunch(k_y_inv_grad<T, N, C, OCC>, dim3(nbk, nb), dim3(SY::NT), st, U1, U2, V3, sc, pred, k * nbk);
   }
   static void y_fwd_div(cx<T>* H1, cx<T>* H2, const cx<T>* H3, const ProbScalars* sc, int pred,
                         int nb, int k, int nslab, hipStream_t st) {
     const int nbk = SY::NBLK / nslab;
-    k_y_fwd_div<T, N, C, OCC><<<dim3(nbk, nb), SY::NT, 0, st>>>(H1, H2, H3, sc, pred, k * nbk);
+    klaunch(k_y_fwd_div<T, N, C, OCC>, dim3(nbk, nb), dim3(SY::NT), st, H1, H2, H3, sc, pred, k * nbk);
   }
   static void x_fwd_div(int mode, const cx<T>* W1, const cx<T>* W23, cx<T>* X, cx<T>* Q,
                         const cx<T>* Sv, const ProbScalars* sc, double* part, double tau, int pred,
@@ -76,16 +100,16 @@ struct SLaunch {
     const dim3 g(SX::NBLK, nb);
     switch (mode) {
       case XM_PCG:
-        k_x_fwd_div<T, N, C, XM_PCG, OCC><<<g, SX::NT, 0, st>>>(W1, W23, X, Q, Sv, sc, part, tau, pred, want_gk);
+        klaunch(k_x_fwd_div<T, N, C, XM_PCG, OCC>, g, dim3(SX::NT), st, W1, W23, X, Q, Sv, sc, part, tau, pred, want_gk);
         break;
       case XM_RHS_FWD:
-        k_x_fwd_div<T, N, C, XM_RHS_FWD, OCC><<<g, SX::NT, 0, st>>>(W1, W23, X, Q, Sv, sc, part, tau, pred, want_gk);
+        klaunch(k_x_fwd_div<T, N, C, XM_RHS_FWD, OCC>, g, dim3(SX::NT), st, W1, W23, X, Q, Sv, sc, part, tau, pred, want_gk);
         break;
       case XM_RHS_ADJ:
-        k_x_fwd_div<T, N, C, XM_RHS_ADJ, OCC><<<g, SX::NT, 0, st>>>(W1, W23, X, Q, Sv, sc, part, tau, pred, want_gk);
+        klaunch(k_x_fwd_div<T, N, C, XM_RHS_ADJ, OCC>, g, dim3(SX::NT), st, W1, W23, X, Q, Sv, sc, part, tau, pred, want_gk);
         break;
       default:
-        k_x_fwd_div<T, N, C, XM_POST_ADJ, OCC><<<g, SX::NT, 0, st>>>(W1, W23, X, Q, Sv, sc, part, tau, pred, want_gk);
+        klaunch(k_x_fwd_div<T, N, C, XM_POST_ADJ, OCC>, g, dim3(SX::NT), st, W1, W23, X, Q, Sv, sc, part, tau, pred, want_gk);
         break;
     }
   }
@@ -138,8 +162,8 @@ struct ZLaunch {
     // FP32 holds all three rows unless an occupancy floor asks for fewer
     // registers; FP64 always streams them one at a time.
     constexpr int PRE = (sizeof(T) == 4 && OCC < 4) ? 3 : 1;
-    k_z_matvec<T, N, ZM::RW, PRE, OCC, EZ, PAIR><<<dim3(nbk, nb), ZM::NT, 0, st>>>(
-        V1, V2, V3, m, m_bs, sc, part, pred, rev, k * nbk);
+    klaunch(k_z_matvec<T, N, ZM::RW, PRE, OCC, EZ, PAIR>, dim3(nbk, nb), dim3(ZM::NT), st,
+            V1, V2, V3, m, m_bs, sc, part, pred, rev, k * nbk);
   }
   template <int MODE>
   static void zs(const ZArgs& a, int nb, hipStream_t st) {

@@ -235,7 +235,8 @@ class Solver final : public ISolver {
           launch_z<ZS_TAN>(a, dc.nb);
         }
         TG_LAUNCH_CHECK();
-        TG_CHECK(step_solve(dc, /*adj=*/false));
+        TG_CHECK(step_solve(dc, /*adj=*/false, est_tan_));
+        est_tan_ = last_its_;
       }
     }
     {
@@ -423,7 +424,7 @@ class Solver final : public ISolver {
   // After a boundary z kernel left the step's real-to-spectral rows in T1
   // (and S for the adjoint): finish the transform into X, run the right-
   // hand-side matvec and the PCG solve.
-  hipError_t step_solve(const Ctx& c, bool adj) {
+  hipError_t step_solve(const Ctx& c, bool adj, int est = -1, bool exact = false) {
     sch_.y_plain(false, c.T1, adj ? c.S : nullptr, c.nb, st_);
     TG_LAUNCH_CHECK();
     sch_.x_fwd_state(c.T1, c.X, c.T2, c.T3, adj ? c.S : nullptr, c.nb, st_);
@@ -436,7 +437,7 @@ class Solver final : public ISolver {
     k_finalize<FIN_INIT><<<c.nb, 256, 0, st_>>>(c.sc, c.part, sch_.xf_nblk, 1.0 / REAL, rtol(),
                                                 maxit());
     TG_LAUNCH_CHECK();
-    return pcg_loop(c);
+    return pcg_loop(c, est, exact);
   }
 
   // In graph mode the iteration budget is the iteration cap, so a solve
@@ -536,9 +537,15 @@ class Solver final : public ISolver {
       launch();
       return;
     }
-    if (hipEventRecord(tm_ev_[2 * tm_used_], st_) != hipSuccess) tm_err_ = true;
+    // the launch records the pair with its own dispatch (klaunch)
+    LaunchEvents& pe = pending_events();
+    pe.start = tm_ev_[2 * tm_used_];
+    pe.stop = tm_ev_[2 * tm_used_ + 1];
     launch();
-    if (hipEventRecord(tm_ev_[2 * tm_used_ + 1], st_) != hipSuccess) tm_err_ = true;
+    if (pe.start != nullptr) {  // not a klaunch launch: no timestamps taken
+      pe.start = pe.stop = nullptr;
+      tm_err_ = true;
+    }
     ++tm_used_;
     ++tm_launches_;
     tm_work_ += work;
@@ -557,7 +564,10 @@ class Solver final : public ISolver {
 
   // Launch predicated iterations in chunks; synchronize only to read the
   // done flags between chunks.
-  hipError_t pcg_loop(const Ctx& c) {
+  // est: expected iteration count of this solve (< 0: the last solve's);
+  // exact: est is the count of an identical earlier solve (a segment
+  // recompute), else one more is launched at once to spare a second check.
+  hipError_t pcg_loop(const Ctx& c, int est = -1, bool exact = false) {
     if (graph_budget_ > 0) {
       // graph capture: a fixed, predicated iteration budget, no host reads;
       // per solve (its last eager count + 25% + 4) when known
@@ -571,7 +581,8 @@ class Solver final : public ISolver {
       return hipGetLastError();
     }
     int launched = 0;
-    int chunk = std::max(1, its_est_);
+    const int base = est >= 0 ? est : its_est_;
+    int chunk = std::max(1, base + (exact ? 0 : 1));
     int maxseen = 0;
     while (launched < d_.maxit) {
       const int k = std::min(chunk, d_.maxit - launched);
@@ -588,9 +599,10 @@ class Solver final : public ISolver {
         call_status_ |= hsc_[b].status;
       }
       if (all) break;
-      chunk = std::max(2, its_est_ / 4);
+      chunk = std::max(2, base / 4);
     }
     its_est_ = std::max(1, maxseen);
+    last_its_ = maxseen;
     its_max_call_ = std::max(its_max_call_, maxseen);
     rec_.push_back(maxseen);
     ++seq_;
@@ -627,7 +639,15 @@ class Solver final : public ISolver {
         launch_z<ZS_FWD>(a, c.nb);
       }
       TG_LAUNCH_CHECK();
-      TG_CHECK(step_solve(c, false));
+      if (initial) {
+        // a recompute repeats these solves exactly: keep their counts
+        TG_CHECK(step_solve(c, false, est_fwd_));
+        if ((int)fwd_its_.size() < d_.nt) fwd_its_.assign(d_.nt, -1);
+        fwd_its_[n] = est_fwd_ = last_its_;
+      } else {
+        const int e = n < (int)fwd_its_.size() ? fwd_its_[n] : -1;
+        TG_CHECK(step_solve(c, false, e, e >= 0));
+      }
     }
     TG_CHECK(inv_xy(c, c.X, c.T1));
     ZArgs a = zargs(c);
@@ -684,7 +704,8 @@ class Solver final : public ISolver {
           k_finalize<FIN_GRHO><<<c.nb, 256, 0, st_>>>(c.sc, c.part, sch_.z_nblk, 1.0, 0, 0);
           TG_LAUNCH_CHECK();
         }
-        TG_CHECK(step_solve(c, true));
+        TG_CHECK(step_solve(c, true, est_adj_));
+        est_adj_ = last_its_;
         if (!gn && qk_ != nullptr) TG_CHECK(coupling_diffusion(c));
         // lam_a = mu + tau k_f A_m mu; g_k += tau <A_m mu, a + b>
         sch_.x_inv_grad(0, c.X, nullptr, c.T1, c.T2, c.sc, nullptr, tau_, 0, c.nb, st_);
@@ -810,6 +831,9 @@ class Solver final : public ISolver {
   double dt_, tau_, h3_;
   std::vector<ProbScalars> hsc_;
   int its_est_;
+  int last_its_ = 0;                  // iterations of the last eager solve
+  int est_fwd_ = -1, est_adj_ = -1, est_tan_ = -1;   // running, per solve kind
+  std::vector<int> fwd_its_;          // per step of the last initial forward
   int live_seg_ = -1;
   int call_status_ = 0;
   int graph_budget_ = 0;
