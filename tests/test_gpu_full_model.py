@@ -144,3 +144,23 @@ def test_full_model_batch_equals_single_fp64():
         assert abs(J[b] - J1) < 1e-12 * abs(J1)
         assert rel(gp[b], gp1) < 1e-12
         assert abs(gr[b] - gr1) < 1e-12 * abs(gr1) and abs(gk[b] - gk1) < 1e-12 * abs(gk1)
+
+
+def test_zero_mask_and_zero_reaction_fp64():
+    """phi_mask = 0 gives c(0) = 0, which the model keeps (c = 0 is a
+    fixed point), and g_p = 0 exactly; a zero reaction field with the
+    same diffusion field is pure Crank-Nicolson diffusion (mass kept)."""
+    print("case full_model degenerate fields", flush=True)
+    n = 16
+    pr, p, mk, mr, mask, tis, pat = full_case(n, 9, 3, 8.0, 0.2)
+    plan = api.Plan(n, 3, pr.centres, pr.sigma, rtol=1e-13, precision="fp64")
+    cT = plan.forward(p, pr.rho_f, pr.k_f, mk, m_react=mr, phi_mask=np.zeros_like(mask))
+    assert float(cT.abs().max()) == 0.0
+    d = inputs.threshold_mask(inputs.random_field(n, 9) + 0.5)
+    _, gp, _, _ = plan.adjoint_misfit(d, labels=labels_arrays(tis, pat))
+    assert float(gp.abs().max()) == 0.0
+    su = oracle_setup(pr, mk, np.zeros_like(mr), None)
+    tr = tumor.forward(su, p)
+    cT = plan.forward(p, pr.rho_f, pr.k_f, mk, m_react=np.zeros_like(mr)).cpu().numpy()
+    assert rel(cT, tr.c[-1]) < 1e-10
+    assert abs(cT.sum() - tr.c[0].sum()) < 1e-12 * abs(tr.c[0].sum())

@@ -150,3 +150,32 @@ def test_transport_errors():
     batch._bind()
     assert L.tg_transport(batch._h, 2, 1, api._ptr(v), None, api._ptr(m), None,
                           api._ptr(small), 1024, None) == _lib.TG_ERR_ARG
+
+
+def test_zero_velocity_is_the_identity_fp64():
+    """v = 0: every foot is the grid point itself, so the state and the
+    adjoint are copied bit for bit and the body force is lam(1) grad m0
+    (the trapezoid weights sum to 1)."""
+    print("case transport zero velocity", flush=True)
+    n = 32
+    m0 = np.stack(inputs.tissues(n, 9)[:2])
+    X, Y, Z = grid(n)
+    lam1 = np.stack([np.cos(X + Z), np.sin(Y)])
+    plan = plan_for(n, "fp64")
+    m1 = plan.transport(np.zeros((3, n, n, n)), m0, 3).cpu().numpy()
+    lam0, body = (x.cpu().numpy() for x in plan.transport_adjoint(lam1))
+    assert np.array_equal(m1, m0) and np.array_equal(lam0, lam1)
+    want = [sum(lam1[l] * spectral.grad(m0[l])[j] for l in range(2)) for j in range(3)]
+    assert max(rel(body[j], want[j]) for j in range(3)) < 1e-12
+
+
+def test_single_step_single_label_fp32():
+    print("case transport one step one label", flush=True)
+    v, w, m0, lam1 = case(32)
+    tr = transport.forward(v, m0[:1], 1)
+    lam0, b, _ = transport.adjoint(v, w, tr, lam1[:1])
+    plan = plan_for(32, "fp32")
+    m1 = plan.transport(np.stack(v), m0[0], 1, w=w).cpu().numpy()
+    g0, gb = (x.cpu().numpy() for x in plan.transport_adjoint(lam1[0]))
+    assert rel(m1[0], tr.m[-1][0]) < 1e-5 and rel(g0[0], lam0[0]) < 1e-5
+    assert max(rel(gb[j], b[j]) for j in range(3)) < 1e-5
