@@ -5,7 +5,11 @@
  * biophysical tumor growth model calibration", arXiv:1907.07774).
  *
  * Model (Sec. 2.1, tumor forward operator with the white-matter-only
- * coefficients of Sec. 4.1), on the periodic cube [0, 2 pi)^3:
+ * coefficients of Sec. 4.1; tg_forward_fields takes the tissue-weighted
+ * coefficients and the CSF mask of Sec. 2.1, tg_adjoint_misfit_labels the
+ * anatomy-label misfit, tg_vjp_coupling the coupling field q(x), and
+ * tg_transport the registration transport), on the periodic cube
+ * [0, 2 pi)^3:
  *     dc/dt = div(k_f m grad c) + rho_f m c (1 - c),   c(0) = Phi p,
  * with Phi p = sum_i p_i exp(-|x - x_i|^2 / (2 sigma^2)) (periodic minimum
  * image distance, peak value 1).  Discretization (Sec. 3.3): Fourier
@@ -27,8 +31,10 @@
  *   - Parameter vectors (p, rho_f, k_f, gradients) are double in both
  *     precisions, stacked per problem (p: [B][n_p], rho_f and k_f: [B]).
  *   - All array arguments are DEVICE pointers owned by the caller; the
- *     library never allocates or frees device memory.  Its only device
- *     storage is the workspace given to tg_plan_bind.
+ *     library never allocates or frees device memory.  Its device storage
+ *     is the workspace given to tg_plan_bind, the transport workspace
+ *     given to tg_transport, and a static table of 512 FFT twiddle factors
+ *     per precision (filled by tg_plan_bind).
  *   - stream is a hipStream_t passed as void*.  Work is enqueued on it; the
  *     PCG loops synchronize that stream between blocks of iterations to
  *     read convergence flags, so calls return after the solves finished
@@ -258,9 +264,10 @@ tg_status tg_stats(tg_plan* plan, tg_solve_stats* out);
  * PCG iteration (1: x-pass inverse with direction update and |p|^2,
  * 2: y-pass inverse, 3: z-pass C2R * m * R2C with the m |grad p|^2 sum,
  * 4: y-pass forward, 5: x-pass forward with the iterate and residual
- * update; 0: off).  While enabled, every
- * launch of that kernel is bracketed by HIP events on the plan's stream.
- * tg_kernel_timer resets the counters. */
+ * update; 0: off).  While enabled, every launch of that kernel carries a
+ * pair of HIP events that take the kernel dispatch's own start and end
+ * timestamps (hipExtLaunchKernelGGL): no extra packets on the plan's
+ * stream.  tg_kernel_timer resets the counters. */
 tg_status tg_kernel_timer(tg_plan* plan, int kernel_id);
 
 /* Read the timer (synchronizes the recorded events): total event time in
