@@ -33,8 +33,8 @@
  *   - All array arguments are DEVICE pointers owned by the caller; the
  *     library never allocates or frees device memory.  Its device storage
  *     is the workspace given to tg_plan_bind, the transport workspace
- *     given to tg_transport, and a static table of 512 FFT twiddle factors
- *     per precision (filled by tg_plan_bind).
+ *     given to tg_transport, and static tables of 512 FFT twiddle factors
+ *     per precision and grid size (filled by tg_plan_bind).
  *   - stream is a hipStream_t passed as void*.  Work is enqueued on it; the
  *     PCG loops synchronize that stream between blocks of iterations to
  *     read convergence flags, so calls return after the solves finished
