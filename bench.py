@@ -307,10 +307,24 @@ def batch_workload(torch, np, api, inputs, reps):
     torch.cuda.synchronize()
     t_graph = (time.perf_counter() - t0) / reps
     status = [pl.stats().status_bits for pl in bg.plans]
+    # PCG iterations of one eager pass (untimed): each one moves 29 fields
+    # of n^3 FP32 values per problem, the algorithmic bytes of the solves
+    pcg_bytes = 0.0
+    its_all = 0
+    for plan, p, rho, kf, m, cobs in items:
+        plan.forward(p, rho, kf, m)
+        its = plan.stats().pcg_its_total
+        plan.adjoint_misfit(cobs)
+        its += plan.stats().pcg_its_total
+        its_all += its
+        pcg_bytes += its * 29.0 * plan.n ** 3 * 4
     return {"problems": 48, "workload": "32 x 64^3 + 16 x 128^3, nt=16, FP32-mixed, ckpt 4",
             "graph_s_per_batch": t_graph, "graph_gradients_per_s": 48.0 / t_graph,
             "eager_s_per_batch": t_eager, "eager_gradients_per_s": 48.0 / t_eager,
-            "capture_s": t_capture, "status_bits": status, "replays": reps}
+            "capture_s": t_capture, "status_bits": status, "replays": reps,
+            "pcg_iterations": its_all,
+            "pcg_algorithmic_GB_s_eager": pcg_bytes / t_eager / 1e9,
+            "pcg_algorithmic_GB_s_graph": pcg_bytes / t_graph / 1e9}
 
 
 def hvp_workload(torch, api, inputs, pr, args):
