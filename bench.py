@@ -349,6 +349,7 @@ def hvp_workload(torch, api, inputs, pr, args):
     torch.cuda.empty_cache()
     return {"directions": 8, "seconds": t, "hvp_per_s": 8.0 / t,
             "pcg_its": st.pcg_its_total, "solves": st.solves,
+            "pcg_algorithmic_GB_s": st.pcg_its_total * 29.0 * pr.n ** 3 * 4 / t / 1e9,
             "symmetry_rel_err": sym, "status_bits": st.status_bits}
 
 
