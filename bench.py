@@ -512,6 +512,19 @@ def main():
     torch.cuda.synchronize()
     copy_gbs = 5 * 2 * (1 << 30) / (ce0.elapsed_time(ce1) * 1e-3) / 1e9
     del a, b
+    # the same traffic as the 7-field PCG passes with no other work: five
+    # fields of the grid read, two written, over sets rotated through 3 GiB
+    # (more than the last-level cache) so that every launch streams from HBM
+    import ctypes
+    from paper_1907_07774_amd import _lib
+    buf = torch.empty(3 << 30, dtype=torch.uint8, device=dev)
+    s7 = ctypes.c_double()
+    _lib.check(_lib.lib().tg_stream_probe(ctypes.c_void_p(buf.data_ptr()), buf.numel(),
+                                          args.n ** 3 * 4, 12, ctypes.byref(s7),
+                                          ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)),
+               "tg_stream_probe")
+    stream7_gbs = s7.value
+    del buf
     torch.cuda.empty_cache()
 
     r32 = run_precision(torch, api, inputs, pr, c_obs, "fp32", args, args.steps, args.warmup,
@@ -538,7 +551,8 @@ def main():
                 "avg_launch_ms": avg_ms, "launches": t["launches"],
                 "work_launches": t["work_bytes"] / unit,
                 "algorithmic_bytes_per_work_launch": unit,
-                "measured_copy_GB_s": copy_gbs, "frac_of_copy": achieved / copy_gbs}
+                "measured_copy_GB_s": copy_gbs, "frac_of_copy": achieved / copy_gbs,
+                "measured_stream7_GB_s": stream7_gbs, "frac_of_stream7": achieved / stream7_gbs}
 
     out = {
         "metric": METRIC,

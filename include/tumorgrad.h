@@ -270,6 +270,19 @@ tg_status tg_stats(tg_plan* plan, tg_solve_stats* out);
  * stream.  tg_kernel_timer resets the counters. */
 tg_status tg_kernel_timer(tg_plan* plan, int kernel_id);
 
+/* Streaming reference for the roofline of the PCG passes (measurement
+ * only, no part of the method): a kernel that reads five and writes two
+ * FP32 fields of field_bytes each in one pass, with no other work, timed
+ * over reps launches on stream (synchronous).  d_buf (caller-owned device
+ * memory, 16-byte aligned) is cut into bytes / (7 field_bytes) sets of
+ * seven fields used in turn, so with d_buf several times the 256 MB
+ * last-level cache every launch streams from HBM; its contents are
+ * overwritten.  Writes the algorithmic GB/s (7 field_bytes per launch).
+ * Errors: TG_ERR_ARG (no complete set, reps < 1, field_bytes < 1024 or not
+ * a multiple of 16), TG_ERR_HIP. */
+tg_status tg_stream_probe(void* d_buf, size_t bytes, size_t field_bytes, int reps,
+                          double* gb_per_s, void* stream);
+
 /* Read the timer (synchronizes the recorded events): total event time in
  * ms, number of timed launches, and the algorithmic HBM bytes those
  * launches moved (launches that did work x fields read and written). */

@@ -29,6 +29,7 @@ EXPORTS = (
     "tg_kernel_timer_read", "tg_plan_set_schedule", "tg_plan_get_schedule",
     "tg_plan_set_pass", "tg_plan_get_pass", "tg_forward_fields", "tg_adjoint_misfit_labels",
     "tg_vjp_coupling", "tg_transport_workspace_bytes", "tg_transport", "tg_transport_adjoint",
+    "tg_stream_probe",
     "tg_batch_capture", "tg_batch_launch", "tg_batch_destroy",
 )
 
@@ -84,6 +85,7 @@ def lib():
     L.tg_transport_workspace_bytes.argtypes = [vp, C.c_int, C.c_int, C.POINTER(sz)]
     L.tg_transport.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp, vp, vp, sz, vp]
     L.tg_transport_adjoint.argtypes = [vp, vp, vp, vp, vp]
+    L.tg_stream_probe.argtypes = [vp, sz, sz, C.c_int, dp, vp]
     L.tg_adjoint_misfit_labels.argtypes = [vp, vp, C.c_int, vp, vp, vp, vp, vp, vp, vp]
     L.tg_hessvec_gn.argtypes = [vp, C.c_int, vp, vp, vp]
     L.tg_stats.argtypes = [vp, C.POINTER(TgSolveStats)]

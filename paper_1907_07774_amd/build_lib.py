@@ -30,7 +30,8 @@ GRIDS = (8, 16, 32, 64, 128, 256)
 # one translation unit per (precision, grid size), plus the host layers
 UNITS = ([("tg_inst.hip", DEV_FLAGS + [f"-DTG_FP64={p}", f"-DTG_N={n}"], f"tg_inst_{p}_{n}")
           for p in (0, 1) for n in GRIDS]
-         + [("tg_dispatch.cpp", HOST_FLAGS, "tg_dispatch"), ("tg_api.cpp", HOST_FLAGS, "tg_api")])
+         + [("tg_probe.hip", DEV_FLAGS, "tg_probe"),
+            ("tg_dispatch.cpp", HOST_FLAGS, "tg_dispatch"), ("tg_api.cpp", HOST_FLAGS, "tg_api")])
 
 
 def _compile(src: str, flags: list[str], stem: str) -> str:

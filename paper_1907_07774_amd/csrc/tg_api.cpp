@@ -301,6 +301,40 @@ tg_status tg_transport_adjoint(tg_plan* plan, const void* d_lam1, void* d_lam0, 
   return TG_OK;
 }
 
+
+tg_status tg_stream_probe(void* d_buf, size_t bytes, size_t field_bytes, int reps,
+                          double* gb_per_s, void* stream) {
+  if (d_buf == nullptr || gb_per_s == nullptr || reps < 1 || field_bytes < 1024 ||
+      field_bytes % 16 != 0 || ((uintptr_t)d_buf % 16) != 0)
+    return TG_ERR_ARG;
+  const size_t sets = bytes / (7 * field_bytes);
+  if (sets < 1) return TG_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  const long long n4 = (long long)(field_bytes / 16);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return TG_ERR_HIP;
+  auto field = [&](size_t set, int k) {
+    return (void*)((char*)d_buf + (set * 7 + k) * field_bytes);
+  };
+  hipError_t e = hipSuccess;
+  for (int r = -1; r < reps && e == hipSuccess; ++r) {
+    if (r == 0) e = hipEventRecord(e0, st);
+    const size_t set = (size_t)(r + 1) % sets;
+    if (e == hipSuccess)
+      e = tg::stream7_launch(field(set, 0), field(set, 1), field(set, 2), field(set, 3),
+                             field(set, 4), n4, st);
+  }
+  if (e == hipSuccess) e = hipEventRecord(e1, st);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return TG_ERR_HIP;
+  *gb_per_s = 7.0 * (double)field_bytes * reps / (ms * 1e-3) / 1e9;
+  return TG_OK;
+}
+
 tg_status tg_stats(tg_plan* plan, tg_solve_stats* out) {
   if (plan == nullptr || out == nullptr) return TG_ERR_ARG;
   std::memset(out, 0, sizeof(*out));

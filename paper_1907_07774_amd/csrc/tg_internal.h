@@ -67,6 +67,11 @@ struct CallStats {
   double worst_rel_residual;
 };
 
+// Streaming reference kernel (tg_stream_probe): fields of n4 float4 values,
+// a..c and d, e read, d and e written.
+hipError_t stream7_launch(const void* a, const void* b, const void* c, void* d, void* e,
+                          long long n4, hipStream_t st);
+
 class ISolver {
  public:
   virtual ~ISolver() {}
