@@ -57,6 +57,8 @@ def parse():
                     help="skip the coupling-field adjoint leg")
     ap.add_argument("--no-transport", action="store_true",
                     help="skip the registration-transport leg")
+    ap.add_argument("--no-paper-shaped", action="store_true",
+                    help="skip the leg at the paper's own tumor settings")
     ap.add_argument("--batch-reps", type=int, default=3)
     return ap.parse_args()
 
@@ -389,6 +391,36 @@ def coupling_workload(torch, np, api, pr, c_obs, args):
     return res
 
 
+def paper_shaped_workload(torch, np, api, inputs):
+    """Gradient at the paper's own tumor settings (Sec. 4.1, Tab. 2): 128^3,
+    125 Gaussians (5^3, spacing 1.5 sigma, sigma = 2 pi/30), rho_f = 15,
+    k_f = 0.1, dt = 0.01 over T = 0.16 (16 steps), FP32-mixed, checkpoint
+    stride 4; median of 5 gradients after one warm-up."""
+    pr = inputs.problem(128, 5, 3, nt=16, T=0.16, rho_f=15.0, k_f=0.1)
+    dev = torch.device("cuda:0")
+    plan = api.Plan(128, 16, pr.centres, pr.sigma, T=0.16, rtol=1e-8, precision="fp32",
+                    ckpt_stride=4)
+    m = torch.tensor(pr.m, dtype=torch.float32, device=dev)
+    d = (plan.forward(inputs.perturbed_p(pr.p, 3), pr.rho_f, pr.k_f, m) > 0.5).float()
+    ts = []
+    for i in range(6):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.forward(pr.p, pr.rho_f, pr.k_f, m)
+        plan.adjoint_misfit(d)
+        torch.cuda.synchronize()
+        if i:
+            ts.append(time.perf_counter() - t0)
+    st = plan.stats()
+    t = sorted(ts)[len(ts) // 2]
+    del plan
+    torch.cuda.empty_cache()
+    return {"workload": "128^3, 125 Gaussians, rho_f = 15, k_f = 0.1, dt = 0.01, T = 0.16, "
+                        "FP32-mixed, checkpoint stride 4",
+            "seconds_per_gradient": t, "gradients_per_s": 1.0 / t,
+            "pcg_its_adjoint_call": st.pcg_its_total}
+
+
 def transport_workload(torch, np, api, inputs, args):
     """Registration transport at 256^3, FP32: the three tissue maps carried
     by a smooth compressible velocity (up to about two cells per step) over
@@ -615,6 +647,8 @@ def main():
         out["coupling"] = coupling_workload(torch, np, api, pr, c_obs, args)
     if not args.no_transport:
         out["transport"] = transport_workload(torch, np, api, inputs, args)
+    if not args.no_paper_shaped:
+        out["paper_shaped"] = paper_shaped_workload(torch, np, api, inputs)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(pr, r32)
     print(json.dumps(out), flush=True)
