@@ -755,8 +755,11 @@ class Solver final : public ISolver {
   // one semi-Lagrangian step of L fields; w_den: divide by (1 - hdt w)
   void sl_step(const T* src, T* dst, const T* disp, int L, const T* w_den, double hdt) {
     if constexpr (N >= 32) {
-      using TL = SLTile<T, N, 4>;
-      k_sl_step_lds<T, N, 4><<<TL::NBLK, 256, 0, st_>>>(src, dst, disp, L, w_den, hdt);
+      // halo of 3 cells: stencils of points displaced by less than 2 cells
+      // per step stay in the tile (larger ones gather from global memory);
+      // a wider halo costs more in its tile loads than it saves
+      using TL = SLTile<T, N, 3>;
+      k_sl_step_lds<T, N, 3><<<TL::NBLK, 256, 0, st_>>>(src, dst, disp, L, w_den, hdt);
     } else {
       // small grids: direct gathers (the numerator factor is already in src)
       constexpr int GB = (int)((REAL + 255) / 256);

@@ -118,7 +118,7 @@ __global__ void __launch_bounds__(256) k_sl_step(const T* __restrict__ src, T* _
 
 // The same step with the input staged in LDS: an output tile of 8 x 8 x 32
 // points (z fastest) and a halo of H cells per side hold every stencil
-// node of points displaced by up to H - 2 cells; a point whose stencil
+// node of points displaced by less than H - 1 cells; a point whose stencil
 // leaves the tile gathers from global memory instead, so any displacement
 // is handled.  Labels one after another through the same LDS tile.  Only
 // the denominator of the adjoint form is applied here (w_den): its
