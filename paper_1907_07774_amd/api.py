@@ -366,6 +366,44 @@ class TumorSolve(torch.autograd.Function):
                 gk.reshape(kf.shape).to(kf.dtype), gm, None)
 
 
+class TumorSolveFields(torch.autograd.Function):
+    """c(T) = TumorSolveFields.apply(p, rho_f, k_f, m_diff, m_react,
+    phi_mask, plan): the full coefficient model (tissue-weighted diffusion
+    field m_diff and reaction field m_react, basis masked by phi_mask,
+    which may be None).  Differentiable in p, rho_f, k_f, m_diff and
+    m_react through the library's discrete adjoint (the field gradients are
+    the coupling fields q_diff and q_react); phi_mask is data."""
+
+    @staticmethod
+    def forward(ctx, p, rho_f, k_f, m_diff, m_react, phi_mask, plan: Plan):
+        mask = None if phi_mask is None else phi_mask.detach()
+        args = (p.detach(), rho_f.detach(), k_f.detach(), m_diff.detach(), m_react.detach())
+        cT = plan.forward(*args[:4], m_react=args[4], phi_mask=mask)
+        ctx.plan = plan
+        ctx.gen = plan.generation
+        ctx.mask = mask
+        ctx.save_for_backward(*args)
+        return cT.clone()
+
+    @staticmethod
+    def backward(ctx, grad_cT):
+        plan: Plan = ctx.plan
+        p, rho, kf, md, mr = ctx.saved_tensors
+        if plan.generation != ctx.gen:
+            # another forward used the plan since: rebuild this trajectory
+            plan.forward(p, rho, kf, md, m_react=mr, phi_mask=ctx.mask)
+            ctx.gen = plan.generation
+        gd = gr_field = None
+        if ctx.needs_input_grad[3] or ctx.needs_input_grad[4]:
+            gp, gr, gk, qd, qr = plan.vjp(grad_cT.detach(), coupling=True)
+            gd = qd.reshape(md.shape).to(md.dtype) if ctx.needs_input_grad[3] else None
+            gr_field = qr.reshape(mr.shape).to(mr.dtype) if ctx.needs_input_grad[4] else None
+        else:
+            gp, gr, gk = plan.vjp(grad_cT.detach())
+        return (gp.view_as(p).to(p.dtype), gr.reshape(rho.shape).to(rho.dtype),
+                gk.reshape(kf.shape).to(kf.dtype), gd, gr_field, None, None)
+
+
 class BatchGraph:
     """Gradient evaluations (forward + misfit + adjoint) of several plans
     captured into one HIP graph and replayed with one launch.

@@ -150,3 +150,34 @@ def test_coupling_identities_256_fp32():
     assert abs(sr - pr.rho_f * float(gr)) < 1e-4 * abs(pr.rho_f * float(gr))
     del plan
     torch.cuda.empty_cache()
+
+
+def test_autograd_full_model_fields_fp64():
+    """TumorSolveFields: gradients in p, rho_f, k_f, the diffusion field and
+    the reaction field of the full model (masked basis) against the
+    oracle, for a loss of c(T) written in torch."""
+    print("case coupling autograd full model fp64 n=16", flush=True)
+    n, nt = 16, 3
+    pr = inputs.problem(n, 2, 27, nt=nt, rho_f=7.0, k_f=0.15)
+    tis = inputs.tissues(n, 27)
+    mk, mr = tumor.coefficient_fields(tis, (1.0, 0.1, 0.0), (1.0, 0.3, 0.0))
+    mask = tumor.csf_mask(tis[2])
+    p = pr.p / max((mask * tumor.phi(pr.p, pr.centres, pr.sigma, n)).max(), 1.0)
+    su = tumor.Setup(mk, pr.centres, pr.sigma, pr.rho_f, pr.k_f, nt, rtol=1e-13, m_rho=mr,
+                     phi_mask=mask)
+    tr = tumor.forward(su, p)
+    lam = inputs.random_field(n, 27)
+    g = tumor.vjp(su, tr, lam, fields=True)
+    plan = api.Plan(n, nt, pr.centres, pr.sigma, rtol=1e-13, precision="fp64")
+    dev = torch.device("cuda:0")
+    t = lambda a, grad=True: torch.tensor(a, dtype=torch.float64, device=dev, requires_grad=grad)
+    pt, rt, kt = t(p), t([pr.rho_f]), t([pr.k_f])
+    mdt, mrt = t(mk), t(mr)
+    cT = api.TumorSolveFields.apply(pt, rt, kt, mdt, mrt, t(mask, False), plan)
+    assert rel(cT.detach().cpu().numpy(), tr.c[-1]) < 1e-10
+    (cT * torch.tensor(lam, device=dev)).sum().backward()
+    assert rel(pt.grad.cpu().numpy(), g.g_p) < 1e-10
+    assert abs(float(rt.grad) - g.g_rho) < 1e-10 * abs(g.g_rho)
+    assert abs(float(kt.grad) - g.g_k) < 1e-10 * abs(g.g_k)
+    assert rel(mdt.grad.cpu().numpy(), g.g_mdiff) < 1e-10
+    assert rel(mrt.grad.cpu().numpy(), g.g_mreact) < 1e-10
