@@ -59,6 +59,8 @@ def parse():
                     help="skip the registration-transport leg")
     ap.add_argument("--no-paper-shaped", action="store_true",
                     help="skip the leg at the paper's own tumor settings")
+    ap.add_argument("--no-full-model", action="store_true",
+                    help="skip the full coefficient and misfit model leg")
     ap.add_argument("--batch-reps", type=int, default=3)
     return ap.parse_args()
 
@@ -391,6 +393,44 @@ def coupling_workload(torch, np, api, pr, c_obs, args):
     return res
 
 
+def full_model_workload(torch, np, api, inputs, pr, args):
+    """Gradient of the full coefficient and misfit model on the benchmark
+    workload (256^3, nt = 32, FP32-mixed, checkpoint stride 4): diffusion
+    field WM + 0.1 GM and reaction field WM + 0.3 GM from seeded tissue
+    maps, basis masked by 1 - CSF, misfit with the three anatomy labels
+    against another seed's maps.  Median of 3 gradients after one warm-up."""
+    dev = torch.device("cuda:0")
+    tis = [torch.tensor(t, dtype=torch.float32, device=dev) for t in inputs.tissues(pr.n, args.seed)]
+    pat = torch.tensor(np.stack(inputs.tissues(pr.n, args.seed + 100)), dtype=torch.float32,
+                       device=dev)
+    md = tis[0] + 0.1 * tis[1]
+    mr = tis[0] + 0.3 * tis[1]
+    mask = 1.0 - tis[2]
+    lab = torch.stack(tis)
+    plan = api.Plan(pr.n, pr.nt, pr.centres, pr.sigma, T=pr.T, rtol=args.rtol,
+                    ckpt_stride=args.ckpt, precision="fp32")
+    d = (plan.forward(inputs.perturbed_p(pr.p, args.seed), pr.rho_f, pr.k_f, md, m_react=mr,
+                      phi_mask=mask) > 0.5).float()
+    ts = []
+    for i in range(4):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.forward(pr.p, pr.rho_f, pr.k_f, md, m_react=mr, phi_mask=mask)
+        plan.adjoint_misfit(d, labels=(lab, pat))
+        torch.cuda.synchronize()
+        if i:
+            ts.append(time.perf_counter() - t0)
+    st = plan.stats()
+    t = sorted(ts)[1]
+    del plan, tis, pat, md, mr, mask, lab, d
+    torch.cuda.empty_cache()
+    return {"workload": "256^3, nt = 32, 64 Gaussians, FP32-mixed, checkpoint stride 4; "
+                        "tissue-weighted diffusion and reaction fields, CSF-masked basis, "
+                        "three-label misfit",
+            "seconds_per_gradient": t, "gradients_per_s": 1.0 / t,
+            "pcg_its_adjoint_call": st.pcg_its_total}
+
+
 def paper_shaped_workload(torch, np, api, inputs):
     """Gradient at the paper's own tumor settings (Sec. 4.1, Tab. 2): 128^3,
     125 Gaussians (5^3, spacing 1.5 sigma, sigma = 2 pi/30), rho_f = 15,
@@ -649,6 +689,8 @@ def main():
         out["transport"] = transport_workload(torch, np, api, inputs, args)
     if not args.no_paper_shaped:
         out["paper_shaped"] = paper_shaped_workload(torch, np, api, inputs)
+    if not args.no_full_model:
+        out["full_model"] = full_model_workload(torch, np, api, inputs, pr, args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(pr, r32)
     print(json.dumps(out), flush=True)
