@@ -266,7 +266,7 @@ tg_status tg_transport_workspace_bytes(const tg_plan* plan, int nt_r, int n_labe
   if (plan == nullptr || bytes == nullptr || nt_r < 1 || n_labels < 1) return TG_ERR_ARG;
   const size_t es = plan->d.prec == TG_FP64 ? 8 : 4;
   const size_t n3 = (size_t)plan->d.n * plan->d.n * plan->d.n;
-  *bytes = ((size_t)(nt_r + 1) * n_labels + 6 + 2 * (size_t)n_labels) * n3 * es;
+  *bytes = ((size_t)(nt_r + 1) * n_labels + 9 + 2 * (size_t)n_labels) * n3 * es;
   return TG_OK;
 }
 

@@ -91,8 +91,8 @@ class ISolver {
   virtual hipError_t hessvec(int ndir, const double* V, double* HV, hipStream_t st) = 0;
   // Registration transport (batch 1): L label fields m0 ([L][n^3]) carried
   // by the stationary velocity v ([3][n^3]) over ntr steps of 1/ntr; m1
-  // receives the last level.  tws: [(ntr + 1) L + 6 + 2 L][n^3] reals
-  // (trajectory, the two feet, two adjoint levels).  w = div v (null: 0)
+  // receives the last level.  tws: [(ntr + 1) L + 6 + 2 L + 3][n^3] reals
+  // (trajectory, the two feet, two adjoint levels, foot scratch).  w = div v (null: 0)
   // is used by the adjoint.
   virtual hipError_t transport(int ntr, int L, const void* v, const void* w, const void* m0,
                                void* m1, void* tws, hipStream_t st) = 0;

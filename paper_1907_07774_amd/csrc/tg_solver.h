@@ -264,10 +264,8 @@ class Solver final : public ISolver {
     tr_ws_ = (T*)tws;
     const double dt = 1.0 / ntr, h = 2.0 * M_PI / N;
     constexpr int GB = (int)((REAL + 255) / 256);
-    k_sl_foot<T, N><<<GB, 256, 0, st_>>>((const T*)v, tr_disp(0), -dt / h);
-    TG_LAUNCH_CHECK();
-    k_sl_foot<T, N><<<GB, 256, 0, st_>>>((const T*)v, tr_disp(1), dt / h);
-    TG_LAUNCH_CHECK();
+    TG_CHECK(sl_foot((const T*)v, tr_disp(0), -dt / h));
+    TG_CHECK(sl_foot((const T*)v, tr_disp(1), dt / h));
     copy_real(tr_level(0), (const T*)m0, (long long)L * REAL);
     for (int k = 0; k < ntr; ++k) {
       sl_step(tr_level(k), tr_level(k + 1), tr_disp(0), L, nullptr, 0.0);
@@ -770,11 +768,26 @@ class Solver final : public ISolver {
     }
   }
 
+  // Heun foot of the stationary velocity s v (s = +-dt/h): the predictor
+  // displacement into the scratch fields, v interpolated there by the
+  // transport step itself (LDS-tiled from 32^3), then the average in place
+  hipError_t sl_foot(const T* v, T* disp, double s) {
+    const int blocks = (int)std::min<long long>((3 * REAL + 255) / 256, 8192);
+    k_sl_scale3<T><<<blocks, 256, 0, st_>>>(v, tr_scratch(), s, REAL);
+    TG_LAUNCH_CHECK();
+    sl_step(v, disp, tr_scratch(), 3, nullptr, 0.0);
+    TG_LAUNCH_CHECK();
+    k_sl_heun3<T><<<blocks, 256, 0, st_>>>(v, disp, s, REAL);
+    TG_LAUNCH_CHECK();
+    return hipSuccess;
+  }
+
   // transport workspace: levels [(ntr + 1)][L][n^3], feet [2][3][n^3],
-  // adjoint levels [2][L][n^3]
+  // adjoint levels [2][L][n^3], foot scratch [3][n^3]
   T* tr_level(int k) { return tr_ws_ + (size_t)k * tr_L_ * REAL; }
   T* tr_disp(int a) { return tr_level(tr_nt_ + 1) + (size_t)a * 3 * REAL; }
   T* tr_lam(int a) { return tr_disp(2) + (size_t)a * tr_L_ * REAL; }
+  T* tr_scratch() { return tr_lam(2); }
 
   void copy_real(T* dst, const T* src, long long n) {
     // n reals = n / 2 complex (n^3 is even)

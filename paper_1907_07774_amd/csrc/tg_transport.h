@@ -74,28 +74,6 @@ __device__ __forceinline__ void grid_ijk(long long idx, int& i, int& j, int& k) 
   k = (int)(idx % N);
 }
 
-// Foot of the characteristic of s v (s = +-dt/h, v in physical units):
-// X* = x + s v(x), X = x + s/2 (v(x) + v(X*)); disp = X - x (grid units).
-template <typename T, int N>
-__global__ void __launch_bounds__(256) k_sl_foot(const T* __restrict__ v, T* __restrict__ disp,
-                                                 double s_) {
-  constexpr long long R = (long long)N * N * N;
-  const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= R) return;
-  int i, j, k;
-  grid_ijk<N>(idx, i, j, k);
-  const T s = (T)s_;
-  const T vx = v[idx], vy = v[R + idx], vz = v[2 * R + idx];
-  Stencil<T, N> st;
-  st.set((T)i + s * vx, (T)j + s * vy, (T)k + s * vz);
-  const T ux = st.apply(v, nullptr, T(0));
-  const T uy = st.apply(v + R, nullptr, T(0));
-  const T uz = st.apply(v + 2 * R, nullptr, T(0));
-  disp[idx] = T(0.5) * s * (vx + ux);
-  disp[R + idx] = T(0.5) * s * (vy + uy);
-  disp[2 * R + idx] = T(0.5) * s * (vz + uz);
-}
-
 // One transport step of L fields: dst_l(x) = src_l(x + disp(x)).
 // Adjoint form (w != null): dst_l(x) = [src_l (1 + hdt w)](x + disp(x)) /
 // (1 - hdt w(x)), the trapezoid rule for the source lam div v along the
@@ -201,6 +179,26 @@ __global__ void __launch_bounds__(256) k_sl_premul(const T* __restrict__ src, T*
     const T f = T(1) + hdt * w[i];
     for (int l = 0; l < L; ++l) dst[l * R + i] = src[l * R + i] * f;
   }
+}
+
+// Heun foot in three passes around the interpolation step: pred = s v;
+// u = v at x + pred (k_sl_step / k_sl_step_lds on the three components);
+// disp = s/2 (v + u), in place on u.
+template <typename T>
+__global__ void __launch_bounds__(256) k_sl_scale3(const T* __restrict__ v, T* __restrict__ out,
+                                                   double s_, long long R) {
+  const T s = (T)s_;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < 3 * R;
+       i += (long long)gridDim.x * 256)
+    out[i] = s * v[i];
+}
+template <typename T>
+__global__ void __launch_bounds__(256) k_sl_heun3(const T* __restrict__ v, T* __restrict__ u,
+                                                  double s_, long long R) {
+  const T hs = (T)(0.5 * s_);
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < 3 * R;
+       i += (long long)gridDim.x * 256)
+    u[i] = hs * (v[i] + u[i]);
 }
 
 // dst_l /= (1 - hdt w), the denominator of the adjoint step (small grids).
