@@ -116,3 +116,78 @@ def test_nonfinite_centres_rejected():
     cen[0, 0, 0] = np.nan
     h = C.c_void_p()
     assert _lib.lib().tg_plan_create(C.byref(desc), C.byref(h)) == _lib.TG_ERR_ARG
+
+
+def test_model_and_coupling_calls_check_on_the_host():
+    """tg_forward_fields, tg_vjp_coupling and tg_adjoint_misfit_labels on an
+    unbound plan: argument errors first, then missing workspace or state."""
+    L = _lib.lib()
+    st, h = create(n=32, nt=4)
+    assert st == _lib.TG_OK
+    p = C.c_void_p(8)
+    assert L.tg_forward_fields(h, p, p, p, None, p, p, p, None) == _lib.TG_ERR_ARG
+    assert L.tg_forward_fields(h, p, p, p, p, None, None, None, None) == _lib.TG_ERR_ARG
+    assert L.tg_forward_fields(h, p, p, p, p, None, None, p, None) == _lib.TG_ERR_WORKSPACE
+    assert L.tg_forward_fields(h, p, p, p, p, p, p, p, None) == _lib.TG_ERR_WORKSPACE
+    assert L.tg_vjp_coupling(h, p, p, p, p, p, p, None) == _lib.TG_ERR_STATE
+    assert L.tg_vjp_coupling(h, None, p, p, p, p, p, None) == _lib.TG_ERR_ARG
+    assert L.tg_vjp_coupling(h, p, p, p, None, p, p, None) == _lib.TG_ERR_ARG
+    assert L.tg_adjoint_misfit_labels(h, p, 0, None, None, p, p, p, p, None) == _lib.TG_ERR_STATE
+    assert L.tg_adjoint_misfit_labels(h, p, 3, p, p, p, p, p, p, None) == _lib.TG_ERR_STATE
+    assert L.tg_adjoint_misfit_labels(h, p, -1, p, p, p, p, p, p, None) == _lib.TG_ERR_ARG
+    assert L.tg_adjoint_misfit_labels(h, p, 2, None, p, p, p, p, p, None) == _lib.TG_ERR_ARG
+    assert L.tg_adjoint_misfit_labels(h, p, 2, p, None, p, p, p, p, None) == _lib.TG_ERR_ARG
+    assert L.tg_adjoint_misfit_labels(h, None, 0, None, None, p, p, p, p,
+                                      None) == _lib.TG_ERR_ARG
+    L.tg_plan_destroy(h)
+
+
+@pytest.mark.parametrize("prec,es", [(_lib.TG_FP64, 8), (_lib.TG_FP32_MIXED, 4)])
+def test_transport_workspace_size_and_host_errors(prec, es):
+    """Transport workspace: every time level of every label, the velocity's
+    feet and scratch (9 fields) and two more fields per label."""
+    L = _lib.lib()
+    st, h = create(n=32, nt=4, prec=prec)
+    assert st == _lib.TG_OK
+    nb = C.c_size_t()
+    for nt_r, nl in ((1, 1), (4, 3), (8, 2)):
+        assert L.tg_transport_workspace_bytes(h, nt_r, nl, C.byref(nb)) == _lib.TG_OK
+        assert nb.value == ((nt_r + 1) * nl + 9 + 2 * nl) * 32 ** 3 * es
+    assert L.tg_transport_workspace_bytes(h, 0, 1, C.byref(nb)) == _lib.TG_ERR_ARG
+    assert L.tg_transport_workspace_bytes(h, 1, 0, C.byref(nb)) == _lib.TG_ERR_ARG
+    assert L.tg_transport_workspace_bytes(h, 1, 1, None) == _lib.TG_ERR_ARG
+    L.tg_transport_workspace_bytes(h, 4, 2, C.byref(nb))
+    need = nb.value
+    p, ws = C.c_void_p(8), C.c_void_p(1 << 20)
+    assert L.tg_transport(h, 4, 2, p, None, p, p, ws, need, None) == _lib.TG_ERR_WORKSPACE
+    assert L.tg_transport(h, 4, 2, p, None, p, p, ws, need - 1, None) == _lib.TG_ERR_WORKSPACE
+    assert L.tg_transport(h, 4, 2, p, None, p, p, C.c_void_p((1 << 20) + 64), need,
+                          None) == _lib.TG_ERR_WORKSPACE
+    assert L.tg_transport(h, 0, 2, p, None, p, p, ws, need, None) == _lib.TG_ERR_ARG
+    assert L.tg_transport(h, 4, 0, p, None, p, p, ws, need, None) == _lib.TG_ERR_ARG
+    assert L.tg_transport(h, 4, 2, None, None, p, p, ws, need, None) == _lib.TG_ERR_ARG
+    assert L.tg_transport(h, 4, 2, p, None, None, p, ws, need, None) == _lib.TG_ERR_ARG
+    assert L.tg_transport(h, 4, 2, p, None, p, p, None, need, None) == _lib.TG_ERR_ARG
+    assert L.tg_transport_adjoint(h, p, p, p, None) == _lib.TG_ERR_STATE
+    assert L.tg_transport_adjoint(h, p, None, p, None) == _lib.TG_ERR_ARG
+    assert L.tg_transport_adjoint(h, p, p, None, None) == _lib.TG_ERR_ARG
+    L.tg_plan_destroy(h)
+    st, hb = create(n=32, nt=4, prec=prec, batch=2)
+    assert st == _lib.TG_OK
+    assert L.tg_transport(hb, 4, 2, p, None, p, p, ws, need, None) == _lib.TG_ERR_ARG
+    L.tg_plan_destroy(hb)
+
+
+def test_stream_probe_rejects_bad_arguments():
+    L = _lib.lib()
+    out = C.c_double()
+    buf = C.c_void_p(1 << 20)
+    f = 1 << 16
+    assert L.tg_stream_probe(None, 7 * f, f, 1, C.byref(out), None) == _lib.TG_ERR_ARG
+    assert L.tg_stream_probe(buf, 7 * f, f, 1, None, None) == _lib.TG_ERR_ARG
+    assert L.tg_stream_probe(buf, 7 * f, f, 0, C.byref(out), None) == _lib.TG_ERR_ARG
+    assert L.tg_stream_probe(buf, 7 * f - 16, f, 1, C.byref(out), None) == _lib.TG_ERR_ARG
+    assert L.tg_stream_probe(buf, 7 * 512, 512, 1, C.byref(out), None) == _lib.TG_ERR_ARG
+    assert L.tg_stream_probe(buf, 7 * (f + 8), f + 8, 1, C.byref(out), None) == _lib.TG_ERR_ARG
+    assert L.tg_stream_probe(C.c_void_p((1 << 20) + 8), 7 * f, f, 1, C.byref(out),
+                             None) == _lib.TG_ERR_ARG
