@@ -61,6 +61,8 @@ def parse():
                     help="skip the leg at the paper's own tumor settings")
     ap.add_argument("--no-full-model", action="store_true",
                     help="skip the full coefficient and misfit model leg")
+    ap.add_argument("--no-slab-share", action="store_true",
+                    help="skip the one-GPU-share (x slab) timing of the y-z-y chain")
     ap.add_argument("--batch-reps", type=int, default=3)
     return ap.parse_args()
 
@@ -461,6 +463,39 @@ def paper_shaped_workload(torch, np, api, inputs):
             "pcg_its_adjoint_call": st.pcg_its_total}
 
 
+def slab_share_workload(torch, api, inputs, pr):
+    """One GPU's share of a 256^3 FP32 solve split into x slabs over 8 GPUs:
+    the y-z-y chain of each PCG iteration (the passes that need no
+    exchange) launched over 32 of the 256 x planes, against the same passes
+    over the whole grid.  Kernel timers over one forward solve (nt = 4)."""
+    from paper_1907_07774_amd.autotune import PASSES
+    n, nt, slabs = pr.n, 4, 8
+    chain = ("y_inv_grad", "z_matvec", "y_fwd_div")
+    dev = torch.device("cuda:0")
+    m = torch.tensor(pr.m, dtype=torch.float32, device=dev)
+    out = {"workload": f"{n}^3 FP32, forward solve (nt = {nt}); y-z-y chain over one x slab "
+                       f"of {n // slabs} planes (one GPU's share at {slabs} GPUs) vs the whole grid"}
+    for tag, sch in (("whole_grid", None), ("slab", (16, 2, slabs, 1))):
+        plan = api.Plan(n, nt, pr.centres, pr.sigma, rtol=1e-8, precision="fp32",
+                        schedule=sch)
+        plan.forward(pr.p, pr.rho_f, pr.k_f, m)
+        us = {}
+        for k in chain:
+            plan.kernel_timer(k)
+            plan.forward(pr.p, pr.rho_f, pr.k_f, m)
+            ms, _, wb = plan.kernel_timer_read()
+            plan.kernel_timer(None)
+            grids = wb / (PASSES[k] * n ** 3 * 4)      # grids' worth of work done
+            per = ms * 1e3 / grids
+            us[k] = per / slabs if tag == "slab" else per
+        out[f"{tag}_us"] = us
+        out[f"{tag}_chain_us"] = sum(us.values())
+        del plan
+        torch.cuda.empty_cache()
+    out["slab_over_eighth_of_grid"] = out["slab_chain_us"] / (out["whole_grid_chain_us"] / slabs)
+    return out
+
+
 def transport_workload(torch, np, api, inputs, args):
     """Registration transport at 256^3, FP32: the three tissue maps carried
     by a smooth compressible velocity (up to about two cells per step) over
@@ -691,6 +726,8 @@ def main():
         out["paper_shaped"] = paper_shaped_workload(torch, np, api, inputs)
     if not args.no_full_model:
         out["full_model"] = full_model_workload(torch, np, api, inputs, pr, args)
+    if not args.no_slab_share and pr.n == 256:
+        out["slab_share"] = slab_share_workload(torch, api, inputs, pr)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(pr, r32)
     print(json.dumps(out), flush=True)
