@@ -82,14 +82,22 @@ def foot(v, dt, sign=-1.0):
     grid points after a step dt of the velocity sign * v (v: three
     physical-unit fields): Heun's step,
         X* = x + sign dt v(x),  X = x + sign dt/2 (v(x) + v(X*))."""
+    return foot_at(v, dt, sign, grid_points(v[0].shape[0]))
+
+
+def foot_at(v, dt, sign, idx):
+    """The same departure points for the grid points idx = (i, j, k)
+    (integer-valued arrays of any one shape)."""
     n = v[0].shape[0]
     h = TWO_PI / n
-    X, Y, Z = grid_points(n)
+    X, Y, Z = (np.asarray(a, dtype=np.float64) for a in idx)
+    at = tuple(np.asarray(a).astype(np.int64) for a in idx)
+    vx = [vj[at] for vj in v]
     s = sign * dt / h
-    Xs, Ys, Zs = X + s * v[0], Y + s * v[1], Z + s * v[2]
+    Xs, Ys, Zs = X + s * vx[0], Y + s * vx[1], Z + s * vx[2]
     vs = [interpolate(vj, Xs, Ys, Zs) for vj in v]
-    return (X + 0.5 * s * (v[0] + vs[0]), Y + 0.5 * s * (v[1] + vs[1]),
-            Z + 0.5 * s * (v[2] + vs[2]))
+    return (X + 0.5 * s * (vx[0] + vs[0]), Y + 0.5 * s * (vx[1] + vs[1]),
+            Z + 0.5 * s * (vx[2] + vs[2]))
 
 
 @dataclasses.dataclass

@@ -164,3 +164,48 @@ def test_zero_mask_and_zero_reaction_fp64():
     cT = plan.forward(p, pr.rho_f, pr.k_f, mk, m_react=np.zeros_like(mr)).cpu().numpy()
     assert rel(cT, tr.c[-1]) < 1e-10
     assert abs(cT.sum() - tr.c[0].sum()) < 1e-12 * abs(tr.c[0].sum())
+
+
+def test_full_model_256_fp32_benchmark_configuration():
+    """The full model at the benchmark size and launch configuration
+    (256^3, nt = 32, 64 Gaussians, FP32-mixed, checkpoint stride 4), where
+    the oracle is too slow, through properties that hold at any size: the
+    fused label misfit equals its definition on the returned c(T); the fused
+    adjoint equals the plain adjoint of the same cotangent; and the coupling
+    fields integrate to the scalar gradients (sum m_diff q_diff = k_f g_kf,
+    sum m_react q_react = rho_f g_rho)."""
+    print("case full model 256 fp32 benchmark configuration", flush=True)
+    n = 256
+    pr = inputs.problem(n, 4, 0, nt=32)
+    dev = torch.device("cuda:0")
+    t32 = lambda a: torch.tensor(np.asarray(a), dtype=torch.float32, device=dev)
+    tis = [t32(t) for t in inputs.tissues(n, 0)]
+    pat = t32(np.stack(inputs.tissues(n, 100)))
+    md, mr, mask = tis[0] + 0.1 * tis[1], tis[0] + 0.3 * tis[1], 1.0 - tis[2]
+    lab = torch.stack(tis)
+    plan = api.Plan(n, 32, pr.centres, pr.sigma, rtol=1e-8, precision="fp32", ckpt_stride=4)
+    d = (plan.forward(inputs.perturbed_p(pr.p, 0), pr.rho_f, pr.k_f, md, m_react=mr,
+                      phi_mask=mask) > 0.5).float()
+    cT = plan.forward(pr.p, pr.rho_f, pr.k_f, md, m_react=mr, phi_mask=mask)
+    J, gp, gr, gk = plan.adjoint_misfit(d, labels=(lab, pat))
+    assert plan.stats().status_bits == 0
+    h3 = (2 * np.pi / n) ** 3
+    c = cT.double()
+    e = lab.double() * (1.0 - c) - pat.double()
+    want = 0.5 * h3 * (float(((c - d.double()) ** 2).sum()) + float((e * e).sum()))
+    assert abs(float(J) - want) < 1e-6 * want
+    lamT = (h3 * ((c - d.double()) - (lab.double() * e).sum(0))).float()
+    del c, e
+    gp2, gr2, gk2, qd, qr = plan.vjp(lamT, coupling=True)
+    assert plan.stats().status_bits == 0
+    # the two cotangents differ by FP32 rounding, so the PCG solves may stop
+    # an iteration apart: the FP32-mixed bar
+    assert rel(gp2.cpu().numpy(), gp.cpu().numpy()) < 1e-4
+    assert abs(float(gr2) - float(gr)) < 1e-4 * abs(float(gr))
+    assert abs(float(gk2) - float(gk)) < 1e-4 * abs(float(gk))
+    sd = float((md.double() * qd.double()).sum())
+    sr = float((mr.double() * qr.double()).sum())
+    assert abs(sd - pr.k_f * float(gk2)) < 1e-4 * abs(pr.k_f * float(gk2))
+    assert abs(sr - pr.rho_f * float(gr2)) < 1e-4 * abs(pr.rho_f * float(gr2))
+    del plan
+    torch.cuda.empty_cache()

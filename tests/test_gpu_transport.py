@@ -3,9 +3,10 @@ tg_transport / tg_transport_adjoint.
 
 FP64: the same interpolation and spectral gradients in another order, so
 the state and adjoint agree to rounding (1e-12) and the body force to
-1e-10; FP32: 1e-5 relative.  At 128^3, where the oracle is slow, the
-duality identity <m(1), lam(1)> = <m(0), lam(0)> holds to the scheme's
-accuracy.
+1e-10; FP32: 1e-5 relative.  At 128^3 and at the benchmark's 256^3, where
+the whole-grid oracle is slow, the duality identity
+<m(1), lam(1)> = <m(0), lam(0)> holds to the scheme's accuracy, and at
+256^3 one step matches the oracle at sampled grid points.
 """
 import math
 
@@ -179,3 +180,68 @@ def test_single_step_single_label_fp32():
     g0, gb = (x.cpu().numpy() for x in plan.transport_adjoint(lam1[0]))
     assert rel(m1[0], tr.m[-1][0]) < 1e-5 and rel(g0[0], lam0[0]) < 1e-5
     assert max(rel(gb[j], b[j]) for j in range(3)) < 1e-5
+
+
+def bench_case_256():
+    """The 256^3 transport workload of the benchmark (three tissue labels,
+    velocity of up to about two cells per step at nt = 4), FP32-rounded
+    so that the oracle sees the GPU's inputs."""
+    n, nt = 256, 4
+    X, Y, Z = grid(n)
+    amp = 2.0 * nt * (TWO_PI / n) / 1.6
+    f32 = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)
+    v = [f32(amp * (np.sin(Y) + 0.3 * np.cos(X))), f32(amp * (np.cos(Z) + 0.2 * np.sin(Y))),
+         f32(amp * (np.sin(X) - 0.25 * np.cos(Z)))]
+    w = f32(amp * (-0.3 * np.sin(X) + 0.2 * np.cos(Y) + 0.25 * np.sin(Z)))
+    m0 = f32(np.stack(inputs.tissues(n, 0)))
+    lam1 = f32(np.stack([np.cos(X + Z), np.exp(0.5 * np.sin(Y)), np.sin(X) * np.cos(Z)]))
+    return v, w, m0, lam1
+
+
+def test_transport_256_fp32_benchmark_configuration():
+    """At the benchmark size and launch configuration: the duality identity
+    over 4 steps, and one step of the state and of the adjoint at 512
+    sampled grid points against the oracle's interpolation at the oracle's
+    feet (the oracle evaluates single points)."""
+    print("case transport 256 fp32 benchmark configuration", flush=True)
+    n = 256
+    v, w, m0, lam1 = bench_case_256()
+    dev = torch.device("cuda:0")
+    plan = plan_for(n, "fp32")
+    m1 = plan.transport(np.stack(v), m0, 4, w=w).double()
+    lam0, _ = plan.transport_adjoint(lam1)
+    a = float((m1 * torch.tensor(lam1, device=dev)).sum())
+    b = float((torch.tensor(m0, device=dev) * lam0.double()).sum())
+    assert abs(a - b) < 2e-5 * abs(a)
+    del m1, lam0
+    rng = np.random.default_rng(256)
+    idx = tuple(rng.integers(0, n, 512) for _ in range(3))
+    m1 = plan.transport(np.stack(v), m0, 1, w=w).cpu().numpy()
+    lam0, _ = (x.cpu().numpy() for x in plan.transport_adjoint(lam1))
+    ys = transport.foot_at(v, 1.0, -1.0, idx)
+    ya = transport.foot_at(v, 1.0, +1.0, idx)
+    for l in range(3):
+        want = transport.interpolate(m0[l], *ys)
+        assert np.abs(m1[l][idx] - want).max() < 1e-5 * np.abs(m0[l]).max()
+        src = lam1[l] * (1.0 + 0.5 * w)
+        want = transport.interpolate(src, *ya) / (1.0 - 0.5 * w[idx])
+        assert np.abs(lam0[l][idx] - want).max() < 1e-5 * np.abs(lam1[l]).max()
+    del plan
+    torch.cuda.empty_cache()
+
+
+def test_zero_velocity_256_fp32():
+    """v = 0 at 256^3: state and adjoint are copied bit for bit and the
+    body force is lam(1) grad m0 (oracle spectral gradient)."""
+    print("case transport zero velocity 256", flush=True)
+    n = 256
+    _, _, m0, lam1 = bench_case_256()
+    plan = plan_for(n, "fp32")
+    m1 = plan.transport(np.zeros((3, n, n, n), dtype=np.float32), m0[:1], 2).cpu().numpy()
+    lam0, body = (x.cpu().numpy() for x in plan.transport_adjoint(lam1[:1]))
+    assert np.array_equal(m1[0], m0[0].astype(np.float32))
+    assert np.array_equal(lam0[0], lam1[0].astype(np.float32))
+    g = spectral.grad(m0[0])
+    assert max(rel(body[j], lam1[0] * g[j]) for j in range(3)) < 1e-5
+    del plan
+    torch.cuda.empty_cache()
