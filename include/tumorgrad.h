@@ -292,7 +292,9 @@ tg_status tg_kernel_timer_read(tg_plan* plan, double* total_ms, long long* launc
 /* Batched gradient evaluation as one replayable HIP graph (many problems
  * in one launch): for each plan, forward + misfit + adjoint
  * (tg_forward then tg_adjoint_misfit) on that plan's batch of problems, all
- * captured on `stream` into one graph.  Inside the graph every PCG solve
+ * captured from `stream` into one graph, each plan as an independent branch
+ * (the plans must not share a workspace), so a replay may run the plans
+ * concurrently.  Inside the graph every PCG solve
  * runs a fixed, predicated iteration budget (kernels of converged problems
  * return at once): pcg_budget for every solve, or if 0 each solve's own
  * iteration count in the plan's last eager tg_forward / tg_adjoint_misfit

@@ -437,22 +437,61 @@ tg_status tg_batch_capture(int nplans, tg_plan* const* plans, const tg_batch_io*
     }
     budgets[i] = its;
   }
+  // The plans share nothing, so each is captured on a branch of its own:
+  // plan 0 on `stream`, plan i > 0 on a helper stream forked from it by an
+  // event and joined back at the end.  The graph then holds independent
+  // chains that a replay can run side by side, so one plan's small or
+  // predicated-off launches overlap another's work.  The helper streams
+  // (default priority) and events are only needed while capturing.
   hipStream_t st = (hipStream_t)stream;
-  if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return TG_ERR_HIP;
-  hipError_t e = hipSuccess;
+  std::vector<hipStream_t> br(nplans, st);
+  std::vector<hipEvent_t> ev(nplans, nullptr);   // ev[0]: fork; ev[i]: join of branch i
+  auto release = [&]() {
+    for (int i = 1; i < nplans; ++i)
+      if (br[i] != st) (void)hipStreamDestroy(br[i]);
+    for (hipEvent_t x : ev)
+      if (x) (void)hipEventDestroy(x);
+  };
+  for (int i = 0; i < nplans; ++i) {
+    if (hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) != hipSuccess) {
+      ev[i] = nullptr;
+      release();
+      return TG_ERR_HIP;
+    }
+    if (i > 0 && hipStreamCreateWithFlags(&br[i], hipStreamNonBlocking) != hipSuccess) {
+      br[i] = st;
+      release();
+      return TG_ERR_HIP;
+    }
+  }
+  if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    release();
+    return TG_ERR_HIP;
+  }
+  hipError_t e = nplans > 1 ? hipEventRecord(ev[0], st) : hipSuccess;
+  int forked = 1;
+  for (; forked < nplans && e == hipSuccess; ++forked) e = hipStreamWaitEvent(br[forked], ev[0], 0);
+  if (e != hipSuccess) --forked;   // the failed branch never joined the capture
   for (int i = 0; i < nplans && e == hipSuccess; ++i) {
     tg_plan* p = plans[i];
     const tg_batch_io& b = io[i];
     p->solver->set_graph_budget(budgets[i], pcg_budget == 0);
-    e = p->solver->forward(b.d_p, b.d_rho_f, b.d_k_f, b.d_m, nullptr, nullptr, b.d_cT, st);
+    e = p->solver->forward(b.d_p, b.d_rho_f, b.d_k_f, b.d_m, nullptr, nullptr, b.d_cT, br[i]);
     if (e == hipSuccess)
       e = p->solver->vjp(nullptr, b.d_cobs, 0, nullptr, nullptr, b.d_J, b.d_gp, b.d_grho,
-                         b.d_gkf, nullptr, nullptr, st);
+                         b.d_gkf, nullptr, nullptr, br[i]);
     p->solver->set_graph_budget(0, false);
     p->last_stream = st;
   }
+  // join every forked branch, also after an error, so the capture can end
+  for (int i = 1; i < forked; ++i) {
+    hipError_t ej = hipEventRecord(ev[i], br[i]);
+    if (ej == hipSuccess) ej = hipStreamWaitEvent(st, ev[i], 0);
+    if (e == hipSuccess) e = ej;
+  }
   hipGraph_t graph = nullptr;
   hipError_t e2 = hipStreamEndCapture(st, &graph);
+  release();
   if (e != hipSuccess || e2 != hipSuccess) {
     if (graph) (void)hipGraphDestroy(graph);
     return TG_ERR_HIP;
