@@ -104,8 +104,11 @@ struct SP {
 #define TG_BOUNDS(NT, W) \
   __attribute__((amdgpu_flat_work_group_size(1, NT), amdgpu_waves_per_eu(W)))
 
-#define SP_SETUP(AXV) SP_SETUP_OFF(AXV, 0)
-#define SP_SETUP_OFF(AXV, OFF)                                          \
+// SP_SETUP_EXIT: EXIT (uniform over the workgroup) returns before the
+// twiddle table is filled, so a predicated-off launch costs only its dispatch.
+#define SP_SETUP(AXV) SP_SETUP_EXIT(AXV, 0, false)
+#define SP_SETUP_OFF(AXV, OFF) SP_SETUP_EXIT(AXV, OFF, false)
+#define SP_SETUP_EXIT(AXV, OFF, EXIT)                                   \
   using S = SP<T, N, C, AXV>;                                           \
   constexpr int E = S::E, TT = S::TT, NH = S::NH;                       \
   (void)NH;                                                             \
@@ -114,6 +117,7 @@ struct SP {
   const int col = threadIdx.x % C, t = threadIdx.x / C;                 \
   const int gc = ((int)blockIdx.x + (OFF)) * C + col;                   \
   const long long base = (long long)b * S::SPEC + S::colbase(gc);       \
+  if (EXIT) return;                                                     \
   tw_fill<T>();
 
 // ---- x pass, inverse, gradient prologue of the diffusion matvec.
@@ -125,9 +129,8 @@ __global__ void TG_BOUNDS((SP<T, N, C, 0>::NT), OCC)
 k_x_inv_grad(cx<T>* __restrict__ P, const cx<T>* __restrict__ Rr, cx<T>* __restrict__ U1,
              cx<T>* __restrict__ U2, const ProbScalars* __restrict__ sc, double* __restrict__ part,
              double tau, int pred) {
-  SP_SETUP(0)
+  SP_SETUP_EXIT(0, 0, pred && sc[blockIdx.y].done)
   __shared__ double red[MODE == 1 ? NSLOT * ((S::NT + 63) / 64) : 1];
-  if (pred && sc[b].done) return;
   const int ky = gc / NH, kz = gc % NH;
   const T wy = (T)wfull<N>(ky), wz = (T)kz;
   const T s = T(1) / (T(N) * T(N) * T(N));
@@ -176,8 +179,7 @@ template <typename T, int N, int C, int OCC>
 __global__ void TG_BOUNDS((SP<T, N, C, 1>::NT), OCC)
 k_y_inv_grad(cx<T>* __restrict__ U1, cx<T>* __restrict__ U2, cx<T>* __restrict__ V3,
              const ProbScalars* __restrict__ sc, int pred, int blk0) {
-  SP_SETUP_OFF(1, blk0)
-  if (pred && sc[b].done) return;
+  SP_SETUP_EXIT(1, blk0, pred && sc[blockIdx.y].done)
   cx<T> v[E], u[E], w[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -203,8 +205,7 @@ template <typename T, int N, int C, int OCC>
 __global__ void TG_BOUNDS((SP<T, N, C, 1>::NT), OCC)
 k_y_fwd_div(cx<T>* __restrict__ H1, cx<T>* __restrict__ H2, const cx<T>* __restrict__ H3,
             const ProbScalars* __restrict__ sc, int pred, int blk0) {
-  SP_SETUP_OFF(1, blk0)
-  if (pred && sc[b].done) return;
+  SP_SETUP_EXIT(1, blk0, pred && sc[blockIdx.y].done)
   constexpr bool PRE = sizeof(T) == 4;
   cx<T> v[E], a[E], c[E];
 #pragma unroll
@@ -247,9 +248,8 @@ __global__ void TG_BOUNDS((SP<T, N, C, 0>::NT), OCC)
 k_x_fwd_div(const cx<T>* __restrict__ W1, const cx<T>* __restrict__ W23, cx<T>* __restrict__ X,
             cx<T>* __restrict__ Q, const cx<T>* __restrict__ Sv, const ProbScalars* __restrict__ sc,
             double* __restrict__ part, double tau, int pred, int want_gk) {
-  SP_SETUP(0)
+  SP_SETUP_EXIT(0, 0, pred && sc[blockIdx.y].done)
   __shared__ double red[NSLOT * ((S::NT + 63) / 64)];
-  if (pred && sc[b].done) return;
   const int ky = gc / NH, kz = gc % NH;
   const T wy = (T)wfull<N>(ky), wz = (T)kz;
   const double wgt = kz == 0 ? 1.0 : 2.0;
