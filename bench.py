@@ -580,7 +580,8 @@ def cpu_baseline(pr, res32):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "tumorgrad runs each problem on one GPU: --gpus must be 1 "
+                                   "(independent problems shard across GPUs with no exchange)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
