@@ -235,3 +235,63 @@ def test_config4_batch_equals_single_64():
         assert float(J[s]) == float(J1)
         assert np.array_equal(gp[s].cpu().numpy(), gp1.cpu().numpy())
         assert float(gr[s]) == float(gr1) and float(gk[s]) == float(gk1)
+
+
+def test_config4_full_batch_graph_48():
+    """The benchmark's batched workload in its own launch configuration: 32
+    problems at 64^3 and 16 at 128^3 (seeded phantoms, 8/27/64 Gaussians
+    padded to a common basis with p = 0, nt = 16, checkpoint stride 4,
+    FP32-mixed) as two batched plans in one HIP graph.  Two replays give
+    the eager gradients bit for bit, and sampled problems solved alone, on
+    plans given the batched plan's tile schedule, give the same bits as in
+    the batch (every kernel and reduction is per problem)."""
+    print("case config4 full batch graph", flush=True)
+    dev = torch.device("cuda:0")
+    items, eager, singles = [], [], []
+    for n, nb, seed0 in ((64, 32, 0), (128, 16, 32)):
+        probs = [inputs.problem(n, (2, 3, 4)[(seed0 + s) % 3], seed0 + s, nt=16)
+                 for s in range(nb)]
+        npmax = max(q.p.size for q in probs)
+        cen = np.zeros((nb, npmax, 3))
+        p = np.zeros((nb, npmax))
+        for b, q in enumerate(probs):
+            cen[b, :q.p.size], cen[b, q.p.size:] = q.centres, q.centres[0]
+            p[b, :q.p.size] = q.p
+        plan = api.Plan(n, 16, cen, probs[0].sigma, rtol=1e-8, precision="fp32", batch=nb,
+                        ckpt_stride=4)
+        m = torch.tensor(np.stack([q.m for q in probs]), dtype=torch.float32, device=dev)
+        rho, kf = [q.rho_f for q in probs], [q.k_f for q in probs]
+        pobs = np.stack([np.pad(inputs.perturbed_p(q.p, seed0 + b), (0, npmax - q.p.size))
+                         for b, q in enumerate(probs)])
+        cobs = (plan.forward(pobs, rho, kf, m) > 0.5).to(torch.float32)
+        plan.forward(p, rho, kf, m)
+        J, gp, gr, gk = plan.adjoint_misfit(cobs)
+        assert plan.stats().status_bits == 0
+        eager.append([t.detach().cpu().numpy().copy() for t in (J, gp, gr, gk)])
+        items.append((plan, p, rho, kf, m, cobs))
+        sched = plan.get_schedule()
+        passes = {k: plan.get_pass(k) for k in api.Plan.KERNELS}
+        for b in (0, nb - 1):
+            sp = api.Plan(n, 16, cen[b], probs[0].sigma, rtol=1e-8, precision="fp32",
+                          ckpt_stride=4, schedule=sched, passes=passes)
+            sp.forward(p[b], rho[b], kf[b], m[b])
+            singles.append((len(eager) - 1, b,
+                            [t.detach().cpu().numpy().copy() for t in sp.adjoint_misfit(cobs[b])]))
+            del sp
+    bg = api.BatchGraph(items)
+    for rep in range(2):
+        bg.launch()
+        torch.cuda.synchronize()
+        for got, ref in zip(bg.results(), eager):
+            for a, b in zip(got, ref):
+                assert np.array_equal(a.detach().cpu().numpy().ravel(), b.ravel()), \
+                    f"replay {rep} differs"
+    for pl in bg.plans:
+        assert pl.stats().status_bits == 0
+    for g, b, (J1, gp1, gr1, gk1) in singles:
+        J, gp, gr, gk = eager[g]
+        assert float(J[b]) == float(J1)
+        assert np.array_equal(gp[b], gp1)
+        assert float(gr[b]) == float(gr1) and float(gk[b]) == float(gk1)
+    del bg, items
+    torch.cuda.empty_cache()
