@@ -686,6 +686,10 @@ def main():
         "roofline": roof,
         "pcg": {k: r32[k] for k in ("pcg_its_forward", "solves_forward", "pcg_its_adjoint",
                                     "solves_adjoint", "pcg_its_max", "worst_rel_residual")},
+        # effective rate of the whole gradient: the PCG iterations' algorithmic
+        # bytes (29 fields of n^3 FP32 values each) over the whole step time
+        "pcg_algorithmic_GB_s": (r32["pcg_its_forward"] + r32["pcg_its_adjoint"]) * 29.0
+                                * args.n ** 3 * 4 / (r32["ms_per_step"] * 1e-3) / 1e9,
         "step_ms_median": r32["step_ms_median"], "step_ms_min": r32["step_ms_min"],
         "kernel_rates_fp32": r32["kernel_rates"],
     }
