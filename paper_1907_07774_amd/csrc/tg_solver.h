@@ -757,7 +757,7 @@ class Solver final : public ISolver {
       // per step stay in the tile (larger ones gather from global memory);
       // a wider halo costs more in its tile loads than it saves
       using TL = SLTile<T, N, 3>;
-      k_sl_step_lds<T, N, 3><<<TL::NBLK, 256, 0, st_>>>(src, dst, disp, L, w_den, hdt);
+      k_sl_step_lds<T, N, 3><<<TL::NBLK, 256, 0, st_>>>(src, dst, disp, L, w_den, hdt, 1.0, 0.0);
     } else {
       // small grids: direct gathers (the numerator factor is already in src)
       constexpr int GB = (int)((REAL + 255) / 256);
@@ -768,10 +768,19 @@ class Solver final : public ISolver {
     }
   }
 
-  // Heun foot of the stationary velocity s v (s = +-dt/h): the predictor
-  // displacement into the scratch fields, v interpolated there by the
-  // transport step itself (LDS-tiled from 32^3), then the average in place
+  // Heun foot of the stationary velocity s v (s = +-dt/h).  From 32^3 one
+  // LDS-tiled step forms the predictor, interpolates v there and averages;
+  // smaller grids write the predictor displacement into the scratch fields,
+  // interpolate by direct gathers and average in place.
   hipError_t sl_foot(const T* v, T* disp, double s) {
+    if constexpr (N >= 32) {
+      // one launch: predictor, interpolation and average (see k_sl_step_lds)
+      using TL = SLTile<T, N, 3>;
+      k_sl_step_lds<T, N, 3, true><<<TL::NBLK, 256, 0, st_>>>(v, disp, v, 3, nullptr, 0.0, s,
+                                                               0.5 * s);
+      TG_LAUNCH_CHECK();
+      return hipSuccess;
+    }
     const int blocks = (int)std::min<long long>((3 * REAL + 255) / 256, 8192);
     k_sl_scale3<T><<<blocks, 256, 0, st_>>>(v, tr_scratch(), s, REAL);
     TG_LAUNCH_CHECK();

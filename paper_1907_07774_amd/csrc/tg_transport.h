@@ -101,6 +101,11 @@ __global__ void __launch_bounds__(256) k_sl_step(const T* __restrict__ src, T* _
 // is handled.  Labels one after another through the same LDS tile.  Only
 // the denominator of the adjoint form is applied here (w_den): its
 // numerator's factor (1 + hdt w) is premultiplied into src by k_sl_premul.
+// FOOT: the displacement is dscale * disp and the output is
+// heun * (src_l(x) + interpolated value), src_l(x) read from the tile: with
+// src = disp = v, dscale = s and heun = s / 2 one launch gives the Heun foot
+// s/2 (v(x) + v(x + s v(x))) of the three velocity components.  (A runtime
+// switch for it made the plain steps 12% slower.)
 template <typename T, int N, int H>
 struct SLTile {
   static constexpr int BX = 8, BY = 8, BZ = 32;
@@ -109,11 +114,12 @@ struct SLTile {
   static_assert(N % BZ == 0 && N % BX == 0, "tile must divide the grid");
 };
 
-template <typename T, int N, int H>
+template <typename T, int N, int H, bool FOOT = false>
 __global__ void __launch_bounds__(256) k_sl_step_lds(const T* __restrict__ src,
                                                      T* __restrict__ dst,
                                                      const T* __restrict__ disp, int L,
-                                                     const T* __restrict__ w_den, double hdt_) {
+                                                     const T* __restrict__ w_den, double hdt_,
+                                                     double dscale_, double heun_) {
   using TL = SLTile<T, N, H>;
   constexpr long long R = (long long)N * N * N;
   __shared__ T tile[TL::TX * TL::TY * TL::TZ];
@@ -122,7 +128,9 @@ __global__ void __launch_bounds__(256) k_sl_step_lds(const T* __restrict__ src,
   const int x0 = bx * TL::BX - H, y0 = by * TL::BY - H, z0 = bz * TL::BZ - H;
   const int tz = threadIdx.x & 31, tx = threadIdx.x >> 5;   // 8 x-values, y looped
   const int gx = bx * TL::BX + tx, gz = bz * TL::BZ + tz;
-  const T hdt = (T)hdt_;
+  const T hdt = (T)hdt_, ds = (T)dscale_, hh = (T)heun_;
+  (void)ds;
+  (void)hh;
   for (int l = 0; l < L; ++l) {
     const T* f = src + l * R;
     for (int q = threadIdx.x; q < TL::TX * TL::TY * TL::TZ; q += 256) {
@@ -134,7 +142,16 @@ __global__ void __launch_bounds__(256) k_sl_step_lds(const T* __restrict__ src,
     for (int yy = 0; yy < TL::BY; ++yy) {
       const int gy = by * TL::BY + yy;
       const long long idx = ((long long)gx * N + gy) * N + gz;
-      const T px = (T)gx + disp[idx], py = (T)gy + disp[R + idx], pz = (T)gz + disp[2 * R + idx];
+      T px, py, pz;
+      if constexpr (FOOT) {
+        px = (T)gx + ds * disp[idx];
+        py = (T)gy + ds * disp[R + idx];
+        pz = (T)gz + ds * disp[2 * R + idx];
+      } else {
+        px = (T)gx + disp[idx];
+        py = (T)gy + disp[R + idx];
+        pz = (T)gz + disp[2 * R + idx];
+      }
       const T fx = floor(px), fy = floor(py), fz = floor(pz);
       const int lx = (int)fx - 1 - x0, ly = (int)fy - 1 - y0, lz = (int)fz - 1 - z0;
       T val;
@@ -161,7 +178,11 @@ __global__ void __launch_bounds__(256) k_sl_step_lds(const T* __restrict__ src,
         st.set(px, py, pz);
         val = st.apply(f, nullptr, T(0));
       }
-      if (w_den) val /= T(1) - hdt * w_den[idx];
+      if constexpr (FOOT) {
+        val = hh * (tile[((tx + H) * TL::TY + (yy + H)) * TL::TZ + tz + H] + val);
+      } else {
+        if (w_den) val /= T(1) - hdt * w_den[idx];
+      }
       dst[l * R + idx] = val;
     }
     __syncthreads();
@@ -181,9 +202,10 @@ __global__ void __launch_bounds__(256) k_sl_premul(const T* __restrict__ src, T*
   }
 }
 
-// Heun foot in three passes around the interpolation step: pred = s v;
-// u = v at x + pred (k_sl_step / k_sl_step_lds on the three components);
-// disp = s/2 (v + u), in place on u.
+// Heun foot in three passes around the direct-gather step (grids below
+// 32^3; larger ones do it in one k_sl_step_lds launch): pred = s v;
+// u = v at x + pred (k_sl_step on the three components); disp = s/2 (v + u),
+// in place on u.
 template <typename T>
 __global__ void __launch_bounds__(256) k_sl_scale3(const T* __restrict__ v, T* __restrict__ out,
                                                    double s_, long long R) {
