@@ -1250,27 +1250,52 @@ __global__ void k_basis_factors(const double* __restrict__ centres, long long c_
   g[((size_t)b * n_p + i) * 3 * n + a * n + j] = exp(-d * d / (2.0 * sigma * sigma));
 }
 
-// c0 = w Phi p (w: the CSF mask of Sec. 2.1, or none): one workgroup per
-// (x, y) row chunk; thread = z.
+// c0 = w Phi p (w: the CSF mask of Sec. 2.1, or none).  A workgroup takes
+// RB consecutive (x, y) rows, a thread one z and KR of the rows, so each
+// Gaussian's z factor is loaded once per thread and used for KR rows (the
+// x and y factors are uniform over a row).  Every point sums its terms in
+// the order of i, each term formed as ((p_i gx) gy) gz.
+template <int N>
+struct PhiF {
+  static constexpr int ROWS_T = 256 / N > 0 ? 256 / N : 1;  // rows side by side
+  static constexpr int RB = 16 > ROWS_T ? 16 : ROWS_T;       // rows per block
+  static constexpr int KR = RB / ROWS_T;                     // rows per thread
+  static constexpr int NBLK = N * N / RB;
+};
+
 template <typename T, int N>
 __global__ void __launch_bounds__(256) k_phi(const double* __restrict__ p, long long p_bs,
                                              const double* __restrict__ g, long long g_bs,
                                              const T* __restrict__ mask, long long mask_bs,
                                              T* __restrict__ out, long long out_bs, int n_p) {
-  constexpr int ROWS = 256 / N > 0 ? 256 / N : 1;
+  using F = PhiF<N>;
   const int b = blockIdx.y;
   const int z = threadIdx.x % N;
-  const int r = threadIdx.x / N;
-  const long long rowid = (long long)blockIdx.x * ROWS + r;
-  const int x = (int)(rowid / N), y = (int)(rowid % N);
+  const int r0 = threadIdx.x / N;
   const double* gb = g + b * g_bs;
-  double acc = 0.0;
+  int xs[F::KR], ys[F::KR];
+  double acc[F::KR];
+#pragma unroll
+  for (int k = 0; k < F::KR; ++k) {
+    const long long rowid = (long long)blockIdx.x * F::RB + r0 + k * F::ROWS_T;
+    xs[k] = (int)(rowid / N);
+    ys[k] = (int)(rowid % N);
+    acc[k] = 0.0;
+  }
   for (int i = 0; i < n_p; ++i) {
     const double* gi = gb + (size_t)i * 3 * N;
-    acc += p[b * p_bs + i] * gi[x] * gi[N + y] * gi[2 * N + z];
+    const double pi = p[b * p_bs + i];
+    const double gz = gi[2 * N + z];
+#pragma unroll
+    for (int k = 0; k < F::KR; ++k) acc[k] += pi * gi[xs[k]] * gi[N + ys[k]] * gz;
   }
-  if (mask) acc *= (double)mask[b * mask_bs + rowid * N + z];
-  out[b * out_bs + rowid * N + z] = (T)acc;
+#pragma unroll
+  for (int k = 0; k < F::KR; ++k) {
+    const long long o = ((long long)blockIdx.x * F::RB + r0 + k * F::ROWS_T) * N + z;
+    double v = acc[k];
+    if (mask) v *= (double)mask[b * mask_bs + o];
+    out[b * out_bs + o] = (T)v;
+  }
 }
 
 // Partials of Phi^T lam: block = RB rows, thread = z (or several rows);

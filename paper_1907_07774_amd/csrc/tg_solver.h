@@ -148,8 +148,7 @@ class Solver final : public ISolver {
     k_basis_factors<<<dim3((nf + 255) / 256, d_.batch), 256, 0, st_>>>(
         w_.centres, (long long)d_.n_p * 3, w_.gfac, N, d_.n_p, d_.sigma);
     TG_LAUNCH_CHECK();
-    constexpr int ROWS = 256 / N > 0 ? 256 / N : 1;
-    k_phi<T, N><<<dim3(N * N / ROWS, d_.batch), 256, 0, st_>>>(
+    k_phi<T, N><<<dim3(PhiF<N>::NBLK, d_.batch), 256, 0, st_>>>(
         p, d_.n_p, w_.gfac, (long long)d_.n_p * 3 * N, mask_, REAL, ck(0), REAL, d_.n_p);
     TG_LAUNCH_CHECK();
     TG_CHECK(fwd_steps(c, 0, d_.nt, /*initial=*/true));
@@ -213,9 +212,8 @@ class Solver final : public ISolver {
     // direction scalars inherit k_f, rho_f, kbar of problem 0
     k_copy_dir_scalars<<<(ndir + 63) / 64, 64, 0, st_>>>(w_.sc, dc.sc, ndir);
     TG_LAUNCH_CHECK();
-    constexpr int ROWS = 256 / N > 0 ? 256 / N : 1;
     // dc0 = Phi v for each direction
-    k_phi<T, N><<<dim3(N * N / ROWS, ndir), 256, 0, st_>>>(V, d_.n_p, w_.gfac, 0, mask_, 0,
+    k_phi<T, N><<<dim3(PhiF<N>::NBLK, ndir), 256, 0, st_>>>(V, d_.n_p, w_.gfac, 0, mask_, 0,
                                                           lam(0), REAL, d_.n_p);
     TG_LAUNCH_CHECK();
     // tangent sweep, forward in time
