@@ -56,6 +56,9 @@ size_t layout(const tg_plan& p, char* base, tg::Workspace* w) {
   w->ckb = take(real * d.batch * d.nseg);
   w->segc = take(real * d.batch * d.s);
   w->segb = take(real * d.batch * d.s);
+  w->ahat = take(spec * d.batch);
+  w->incr = take(spec * d.batch);
+  w->ckd = take(spec * d.batch * d.nseg);
   const int bl = d.batch > d.dirs ? d.batch : d.dirs;
   w->lam = take(real * bl);
   w->gfac = (double*)take(sizeof(double) * d.batch * d.n_p * 3 * d.n);

@@ -54,6 +54,9 @@ struct Workspace {
   void* ckb;          // [nseg][batch][n^3] b^{j s - 1} (j >= 1)
   void* segc;         // [s][batch][n^3]  c^n within the live segment
   void* segb;         // [s][batch][n^3]  b^n within the live segment
+  void* ahat;         // [batch][n^3/2] complex: a-hat of the current forward step
+  void* incr;         // [batch][n^3/2] complex: d = b - a of the previous forward step
+  void* ckd;          // [nseg][batch][n^3/2] complex: d entering each segment
   void* lam;          // [max(batch, dirs)][n^3] real scratch field
   double* gfac;       // [batch][n_p][3][n] Gaussian factors
   double* centres;    // [batch][n_p][3]

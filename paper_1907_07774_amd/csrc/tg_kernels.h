@@ -240,7 +240,9 @@ enum XMode : int {
   XM_PCG = 0,      // q = p - tau kf Am; x += alpha p; r -= alpha q; partials <r, M r>, |r|^2
   XM_RHS_FWD = 1,  // x0 = X; r = 2 tau kf Am; partials |rhs|^2, <r, M r>, |r|^2
   XM_RHS_ADJ = 2,  // x0 = X; r = tau kf Am;  rhs = X
-  XM_POST_ADJ = 3  // X += tau kf Am; partial <Am, S> (k_f gradient)
+  XM_POST_ADJ = 3, // X += tau kf Am; partial <Am, S> (k_f gradient)
+  XM_SHIFT = 4     // Am of the shift d = Sv: x0 = X + d, r = Q - d + tau kf Am (the exact
+                   // residual of x0 when Q held r of X); partials |X + Q/2|^2, <r, M r>, |r|^2
 };
 
 template <typename T, int N, int C, int MODE, int OCC>
@@ -286,6 +288,26 @@ k_x_fwd_div(const cx<T>* __restrict__ W1, const cx<T>* __restrict__ W23, cx<T>* 
       const double rr = (double)r.x * (double)r.x + (double)r.y * (double)r.y;
       acc[0] += wgt * (double)pre * rr;
       acc[1] += wgt * rr;
+    }
+  } else if constexpr (MODE == XM_SHIFT) {
+    ns = 3;
+    const T kb = (T)(tau * sc[b].kbar);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int kx = t + TT * e;
+      const long long o = base + kx * S::PSTR;
+      const T wx = (T)wfull<N>(kx);
+      const cx<T> am = mul_i(a[e], wx) + c[e];
+      const cx<T> x0 = X[o], r0 = Q[o], d = Sv[o];
+      const cx<T> rhs = x0 + scale(r0, T(0.5));
+      X[o] = x0 + d;
+      const cx<T> r = r0 - d + scale(am, tk);
+      Q[o] = r;
+      const T pre = T(1) / (T(1) + kb * (wx * wx + wy * wy + wz * wz));
+      const double rr = (double)r.x * (double)r.x + (double)r.y * (double)r.y;
+      acc[0] += wgt * ((double)rhs.x * (double)rhs.x + (double)rhs.y * (double)rhs.y);
+      acc[1] += wgt * (double)pre * rr;
+      acc[2] += wgt * rr;
     }
   } else if constexpr (MODE == XM_RHS_FWD || MODE == XM_RHS_ADJ) {
     ns = 3;
@@ -1231,6 +1253,16 @@ __global__ void __launch_bounds__(256) k_misfit_labels(const T* __restrict__ c,
   }
   block_sums<256>(acc, 1, red);
   if (threadIdx.x == 0) part_at(part, b, 0)[blockIdx.x] = acc[0];
+}
+
+// d = x - a-hat over n complex values: the increment b - a of a forward step.
+template <typename T>
+__global__ void __launch_bounds__(256) k_increment(const cx<T>* __restrict__ X,
+                                                   const cx<T>* __restrict__ Ah,
+                                                   cx<T>* __restrict__ D, long long n) {
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (long long)gridDim.x * 256)
+    D[i] = X[i] - Ah[i];
 }
 
 // Gaussian factors g[b][i][a][j] = exp(-d(x_j, c_ia)^2 / (2 sigma^2)),

@@ -108,6 +108,9 @@ struct SLaunch {
       case XM_RHS_ADJ:
         klaunch(k_x_fwd_div<T, N, C, XM_RHS_ADJ, OCC>, g, dim3(SX::NT), st, W1, W23, X, Q, Sv, sc, part, tau, pred, want_gk);
         break;
+      case XM_SHIFT:
+        klaunch(k_x_fwd_div<T, N, C, XM_SHIFT, OCC>, g, dim3(SX::NT), st, W1, W23, X, Q, Sv, sc, part, tau, pred, want_gk);
+        break;
       default:
         klaunch(k_x_fwd_div<T, N, C, XM_POST_ADJ, OCC>, g, dim3(SX::NT), st, W1, W23, X, Q, Sv, sc, part, tau, pred, want_gk);
         break;

@@ -6,7 +6,10 @@
 // with A = div(k_f m grad .) and R the exact logistic flow.  Each
 // Crank-Nicolson system is solved by PCG in spectral space with the
 // constant-coefficient Fourier preconditioner (1 + dt/2 kbar |w|^2)^-1,
-// kbar = k_f max(m); x0 = a, stop when ||r|| <= rtol ||rhs|| (grid norms).
+// kbar = k_f max(m); stop when ||r|| <= rtol ||rhs|| (grid norms).  The
+// first forward solve starts from x0 = a, later ones from a plus the
+// previous step's increment b - a (exact initial residual), adjoint solves
+// from lambda.
 // The adjoint is the exact transpose of these discrete steps (reduced
 // gradient of Sec. 3.1: state solve, adjoint solve, gradient), with
 // checkpointed states recomputed segment by segment.
@@ -365,6 +368,7 @@ class Solver final : public ISolver {
   T* ckb(int j) { return (T*)w_.ckb + (size_t)j * d_.batch * REAL; }
   T* segc(int i) { return (T*)w_.segc + (size_t)i * d_.batch * REAL; }
   T* segb(int i) { return (T*)w_.segb + (size_t)i * d_.batch * REAL; }
+  cx<T>* ckd(int j) { return (cx<T>*)w_.ckd + (size_t)j * d_.batch * (REAL / 2); }
   T* lam(int b) { return (T*)w_.lam + (size_t)b * REAL; }
   // stored states of the live segment
   T* cn_ptr(int n) { return (n % d_.s == 0) ? ck(n / d_.s) : segc(n % d_.s); }
@@ -420,7 +424,11 @@ class Solver final : public ISolver {
   // After a boundary z kernel left the step's real-to-spectral rows in T1
   // (and S for the adjoint): finish the transform into X, run the right-
   // hand-side matvec and the PCG solve.
-  hipError_t step_solve(const Ctx& c, bool adj, int est = -1, bool exact = false) {
+  // Forward solves of the primary problems (hist bits): 1 starts from
+  // x0 = a + d, d = b - a of the previous step, with the exact residual of
+  // x0 from one matvec on d (XM_SHIFT); 2 keeps this step's d for the next.
+  hipError_t step_solve(const Ctx& c, bool adj, int est = -1, bool exact = false,
+                        int hist = 0) {
     sch_.y_plain(false, c.T1, adj ? c.S : nullptr, c.nb, st_);
     TG_LAUNCH_CHECK();
     sch_.x_fwd_state(c.T1, c.X, c.T2, c.T3, adj ? c.S : nullptr, c.nb, st_);
@@ -430,10 +438,26 @@ class Solver final : public ISolver {
     sch_.x_fwd_div(adj ? XM_RHS_ADJ : XM_RHS_FWD, c.T2, c.T3, c.X, c.R, nullptr, c.sc, c.part, tau_,
                    0, 0, c.nb, st_);
     TG_LAUNCH_CHECK();
+    cx<T>* ah = (cx<T>*)w_.ahat;
+    cx<T>* dd = (cx<T>*)w_.incr;
+    if (hist & 2) copy_spec(c, ah, c.X);
+    if (hist & 1) {
+      sch_.x_inv_grad(0, dd, nullptr, c.T1, c.T2, c.sc, nullptr, tau_, 0, c.nb, st_);
+      matvec_mid(c, c.T1, c.T2, c.T3, 0);
+      sch_.x_fwd_div(XM_SHIFT, c.T1, c.T2, c.X, c.R, dd, c.sc, c.part, tau_, 0, 0, c.nb, st_);
+      TG_LAUNCH_CHECK();
+    }
     k_finalize<FIN_INIT><<<c.nb, 256, 0, st_>>>(c.sc, c.part, sch_.xf_nblk, 1.0 / REAL, rtol(),
                                                 maxit());
     TG_LAUNCH_CHECK();
-    return pcg_loop(c, est, exact);
+    TG_CHECK(pcg_loop(c, est, exact));
+    if (hist & 2) {
+      const long long nc = (long long)c.nb * (REAL / 2);
+      k_increment<T><<<(int)std::min<long long>((nc + 255) / 256, 8192), 256, 0, st_>>>(
+          c.X, ah, dd, nc);
+      TG_LAUNCH_CHECK();
+    }
+    return hipSuccess;
   }
 
   // In graph mode the iteration budget is the iteration cap, so a solve
@@ -616,7 +640,13 @@ class Solver final : public ISolver {
   hipError_t fwd_steps(const Ctx& c, int n0, int n1, bool initial) {
     const int s = d_.s;
     const int last_start = (d_.nseg - 1) * s;
+    // every step after the first starts from the previous step's increment;
+    // a recompute takes the increment entering its segment from where the
+    // initial forward stored it, so it repeats those solves bit for bit
+    if (!initial && n0 > 0) copy_spec(c, (cx<T>*)w_.incr, ckd(n0 / s));
     for (int n = n0; n < n1; ++n) {
+      if (initial && n > 0 && n % s == 0) copy_spec(c, ckd(n / s), (cx<T>*)w_.incr);
+      const int hb = (n > 0 ? 1 : 0) | (n + 1 < d_.nt ? 2 : 0);
       ZArgs a = zargs(c);
       if (n == n0) {
         a.Cin = cn_ptr_for(n, initial); a.cin_bs = c.traj_bs;
@@ -637,12 +667,12 @@ class Solver final : public ISolver {
       TG_LAUNCH_CHECK();
       if (initial) {
         // a recompute repeats these solves exactly: keep their counts
-        TG_CHECK(step_solve(c, false, est_fwd_));
+        TG_CHECK(step_solve(c, false, est_fwd_, false, hb));
         if ((int)fwd_its_.size() < d_.nt) fwd_its_.assign(d_.nt, -1);
         fwd_its_[n] = est_fwd_ = last_its_;
       } else {
         const int e = n < (int)fwd_its_.size() ? fwd_its_[n] : -1;
-        TG_CHECK(step_solve(c, false, e, e >= 0));
+        TG_CHECK(step_solve(c, false, e, e >= 0, hb));
       }
     }
     TG_CHECK(inv_xy(c, c.X, c.T1));

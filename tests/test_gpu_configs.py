@@ -28,10 +28,14 @@ def rel(a, b):
 
 
 # -------------------------------------------------------------- 64^3
-@pytest.mark.parametrize("rtol,tol", [(1e-13, 1e-10), (1e-8, 1e-7)])
+@pytest.mark.parametrize("rtol,tol", [(1e-13, 1e-10), (1e-8, 1e-6)])
 def test_config1_forward_64(rtol, tol):
     """64^3, 8 Gaussians with p ~ U[0,1], rho_f = 10, k_f = 0.1, T = 1,
-    nt = 16.  At rtol 1e-8 two PCG implementations agree to ~kappa 1e-8."""
+    nt = 16.  At rtol 1e-8 the two forward sweeps stop at different PCG
+    iterates (the GPU starts each solve from the previous step's increment,
+    the oracle from a): each is within the solver's error of the converged
+    solution (the oracle's own rtol-1e-8 run is 2e-7 from its rtol-1e-13
+    run), so they are compared at a few times that."""
     print(f"case config1 rtol={rtol}", flush=True)
     pr = inputs.problem(64, 2, 1, nt=16, rho_f=10.0, k_f=0.1)
     su = tumor.Setup(pr.m, pr.centres, pr.sigma, pr.rho_f, pr.k_f, 16, rtol=rtol)
