@@ -33,8 +33,9 @@
  *   - All array arguments are DEVICE pointers owned by the caller; the
  *     library never allocates or frees device memory.  Its device storage
  *     is the workspace given to tg_plan_bind, the transport workspace
- *     given to tg_transport, and static tables of 512 FFT twiddle factors
- *     per precision and grid size (filled by tg_plan_bind).
+ *     given to tg_transport, static tables of 512 FFT twiddle factors
+ *     per precision and grid size (filled by tg_plan_bind), and the static
+ *     scratch of tg_forward_static (TG_STATIC_SCRATCH_BYTES per device).
  *   - stream is a hipStream_t passed as void*.  Work is enqueued on it; the
  *     PCG loops synchronize that stream between blocks of iterations to
  *     read convergence flags, so calls return after the solves finished
@@ -61,7 +62,9 @@ typedef enum {
   TG_ERR_NOT_CONVERGED = 3,  /* a PCG solve reached pcg_maxit */
   TG_ERR_NUMERIC = 4,        /* PCG breakdown or non-finite values */
   TG_ERR_HIP = 5,            /* a HIP runtime call or kernel launch failed */
-  TG_ERR_WORKSPACE = 6       /* workspace missing, too small or misaligned */
+  TG_ERR_WORKSPACE = 6,      /* workspace missing, too small or misaligned */
+  TG_ERR_SCRATCH_LIMIT = 7   /* tg_forward_static: the plan's workspace exceeds
+                                TG_STATIC_SCRATCH_BYTES */
 } tg_status;
 
 typedef enum {
@@ -135,6 +138,42 @@ tg_status tg_forward(tg_plan* plan, const double* d_p, const double* d_rho_f,
 tg_status tg_forward_fields(tg_plan* plan, const double* d_p, const double* d_rho_f,
                             const double* d_k_f, const void* d_m_diff, const void* d_m_react,
                             const void* d_phi_mask, void* d_cT, void* stream);
+
+/* Size of the library's static device scratch, per device (64 MiB): the
+ * largest workspace tg_forward_static accepts (a 64^3 FP32 plan with any
+ * checkpoint stride, or 64^3 FP64 with stride 4, fits). */
+#define TG_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* tg_forward for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Instead of caller memory the plan's workspace is a static device array of
+ * the library, TG_STATIC_SCRATCH_BYTES on every device it runs on, held
+ * until the process ends.  The caller still passes inputs and outputs
+ * exactly as to tg_forward; the plan must have been created
+ * (tg_plan_create) but need not be bound.  Nothing here or in the later
+ * calls on the plan allocates device memory.
+ *   - The first call for a plan on a device binds the plan to that
+ *     device's scratch (synchronous: twiddle table and centres copied, as
+ *     tg_plan_bind does); later calls on the same plan launch like
+ *     tg_forward.  tg_vjp, tg_adjoint_misfit(_labels), tg_hessvec_gn and
+ *     tg_stats then work on the plan as usual.
+ *   - One plan owns a device's scratch at a time.  A call for another plan
+ *     takes the scratch over and leaves the previous owner unbound, as if
+ *     never bound: its trajectory is gone (tg_vjp, tg_adjoint_misfit and
+ *     tg_hessvec_gn return TG_ERR_STATE) and tg_forward returns
+ *     TG_ERR_WORKSPACE until it is bound again (by tg_plan_bind or
+ *     tg_forward_static).  Binding a plan to caller memory or destroying it
+ *     gives the scratch up.
+ *   - The scratch keeps the last call's contents; nothing in it needs to
+ *     start at zero (every buffer is written before it is read).
+ *   - Calls that overlap in time on one device race on the scratch: the
+ *     caller orders them (one stream, or synchronization between streams),
+ *     including the final kernels of the previous owner's last call.
+ * Errors: TG_ERR_ARG (null pointer), TG_ERR_SCRATCH_LIMIT (the plan's
+ * workspace, tg_plan_workspace_bytes, exceeds TG_STATIC_SCRATCH_BYTES;
+ * nothing is bound or launched), TG_ERR_HIP, and those of tg_forward. */
+tg_status tg_forward_static(tg_plan* plan, const double* d_p, const double* d_rho_f,
+                            const double* d_k_f, const void* d_m, void* d_cT, void* stream);
 
 /* Vector-Jacobian product of the last forward (adjoint solve, Sec. 2.1
  * optimality conditions, evaluated as in Sec. 3.1): given a Euclidean

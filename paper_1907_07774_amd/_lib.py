@@ -18,6 +18,7 @@ TG_ERR_NOT_CONVERGED = 3
 TG_ERR_NUMERIC = 4
 TG_ERR_HIP = 5
 TG_ERR_WORKSPACE = 6
+TG_ERR_SCRATCH_LIMIT = 7
 
 TG_FP64 = 0
 TG_FP32_MIXED = 1
@@ -29,7 +30,7 @@ EXPORTS = (
     "tg_kernel_timer_read", "tg_plan_set_schedule", "tg_plan_get_schedule",
     "tg_plan_set_pass", "tg_plan_get_pass", "tg_forward_fields", "tg_adjoint_misfit_labels",
     "tg_vjp_coupling", "tg_transport_workspace_bytes", "tg_transport", "tg_transport_adjoint",
-    "tg_stream_probe",
+    "tg_stream_probe", "tg_forward_static",
     "tg_batch_capture", "tg_batch_launch", "tg_batch_destroy",
 )
 
@@ -78,6 +79,7 @@ def lib():
     L.tg_plan_workspace_bytes.argtypes = [vp, C.POINTER(sz)]
     L.tg_plan_bind.argtypes = [vp, vp, sz]
     L.tg_forward.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.tg_forward_static.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.tg_vjp.argtypes = [vp, vp, vp, vp, vp, vp]
     L.tg_adjoint_misfit.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.tg_forward_fields.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -107,6 +109,7 @@ def lib():
     L.tg_plan_set_pass.argtypes = [vp, C.c_int, C.c_int, C.c_int]
     L.tg_plan_get_pass.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
     for name in ("tg_plan_create", "tg_plan_workspace_bytes", "tg_plan_bind", "tg_forward",
+                 "tg_forward_static",
                  "tg_vjp", "tg_adjoint_misfit", "tg_hessvec_gn", "tg_stats",
                  "tg_kernel_timer", "tg_kernel_timer_read", "tg_plan_set_schedule",
                  "tg_plan_get_schedule", "tg_plan_set_pass", "tg_plan_get_pass",

@@ -28,9 +28,9 @@ HOST_FLAGS = ["-x", "c++", "-O2", "-std=c++17", "-fPIC", "-D__HIP_PLATFORM_AMD__
 
 GRIDS = (8, 16, 32, 64, 128, 256)
 # one translation unit per (precision, grid size), plus the host layers
-UNITS = ([("tg_inst.hip", DEV_FLAGS + [f"-DTG_FP64={p}", f"-DTG_N={n}"], f"tg_inst_{p}_{n}")
+UNITS = ([("tg_inst.hip", DEV_FLAGS + [f"-DTG_INST_FP64={p}", f"-DTG_N={n}"], f"tg_inst_{p}_{n}")
           for p in (0, 1) for n in GRIDS]
-         + [("tg_probe.hip", DEV_FLAGS, "tg_probe"),
+         + [("tg_probe.hip", DEV_FLAGS, "tg_probe"), ("tg_static.hip", DEV_FLAGS, "tg_static"),
             ("tg_dispatch.cpp", HOST_FLAGS, "tg_dispatch"), ("tg_api.cpp", HOST_FLAGS, "tg_api")])
 
 

@@ -108,6 +108,8 @@ const char* tg_status_string(tg_status s) {
     case TG_ERR_NUMERIC: return "PCG breakdown or non-finite values";
     case TG_ERR_HIP: return "HIP runtime error";
     case TG_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
+    case TG_ERR_SCRATCH_LIMIT:
+      return "plan workspace exceeds the static scratch (TG_STATIC_SCRATCH_BYTES)";
   }
   return "unknown status";
 }
@@ -158,6 +160,16 @@ tg_status tg_plan_workspace_bytes(const tg_plan* plan, size_t* bytes) {
 
 tg_status tg_plan_bind(tg_plan* plan, void* d_ws, size_t bytes) {
   if (plan == nullptr) return TG_ERR_ARG;
+  tg::static_scratch_release(plan);
+  return tg::plan_bind_ws(plan, d_ws, bytes);
+}
+
+}  // extern "C"
+
+namespace tg {
+
+tg_status plan_bind_ws(tg_plan* plan, void* d_ws, size_t bytes) {
+  if (plan == nullptr) return TG_ERR_ARG;
   if (d_ws == nullptr || bytes < plan->ws_bytes || ((uintptr_t)d_ws % ALIGN) != 0)
     return TG_ERR_WORKSPACE;
   hipError_t e = ensure_twiddles(plan->d.prec, plan->d.n);
@@ -173,6 +185,21 @@ tg_status tg_plan_bind(tg_plan* plan, void* d_ws, size_t bytes) {
   plan->have_transport = false;
   return TG_OK;
 }
+
+void plan_unbind(tg_plan* plan) {
+  if (plan == nullptr) return;
+  plan->solver.reset();
+  plan->ws = nullptr;
+  plan->w = tg::Workspace{};
+  plan->have_traj = false;
+  plan->have_transport = false;
+}
+
+const void* plan_workspace(const tg_plan* plan) { return plan ? plan->ws : nullptr; }
+
+}  // namespace tg
+
+extern "C" {
 
 tg_status tg_forward_fields(tg_plan* plan, const double* d_p, const double* d_rho_f,
                             const double* d_k_f, const void* d_m_diff, const void* d_m_react,
@@ -529,6 +556,10 @@ void tg_batch_destroy(tg_batch* batch) {
   delete batch;
 }
 
-void tg_plan_destroy(tg_plan* plan) { delete plan; }
+void tg_plan_destroy(tg_plan* plan) {
+  if (plan == nullptr) return;
+  tg::static_scratch_release(plan);
+  delete plan;
+}
 
 }  // extern "C"

@@ -1,8 +1,8 @@
 // One (precision, grid size) instantiation of the solver; compiled once per
-// pair with -DTG_FP64=0|1 -DTG_N=<n>.
+// pair with -DTG_INST_FP64=0|1 -DTG_N=<n>.
 #include "tg_solver.h"
 
-#if TG_FP64
+#if TG_INST_FP64
 using TgReal = double;
 #define TG_SUFFIX(name) TG_CAT(name, TG_CAT(_f64_, TG_N))
 #else

@@ -4,6 +4,8 @@
 #include <cstdint>
 #include <hip/hip_runtime_api.h>
 
+#include "../../include/tumorgrad.h"
+
 namespace tg {
 
 // Per-problem solver scalars kept in device memory.  Dot products, norms,
@@ -136,6 +138,18 @@ enum KernelId : int {
   KT_X_FWD_DIV = 5,
   KT_LAST = KT_X_FWD_DIV
 };
+
+// Plan binding shared by tg_plan_bind and tg_forward_static (host only).
+// plan_bind_ws: bind d_ws as the workspace (tg_plan_bind's checks and
+// set-up, without the static-scratch bookkeeping).  plan_unbind: drop the
+// solver and workspace (the plan must be bound again before use).
+// plan_workspace: the bound workspace or nullptr.
+tg_status plan_bind_ws(tg_plan* plan, void* d_ws, size_t bytes);
+void plan_unbind(tg_plan* plan);
+const void* plan_workspace(const tg_plan* plan);
+// tg_forward_static's bookkeeping: forget `plan` as the owner of any
+// device's static scratch (called when it is rebound or destroyed).
+void static_scratch_release(tg_plan* plan);
 
 // Phi^T partial-block count for grid size n (workspace sizing).
 int phi_blocks_for(int n);

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_function():
 def test_version_and_status_strings():
     L = _lib.lib()
     assert L.tg_version() == 1
-    for s in range(7):
+    for s in range(8):
         assert len(L.tg_status_string(s)) > 0
 
 
@@ -191,3 +191,26 @@ def test_stream_probe_rejects_bad_arguments():
     assert L.tg_stream_probe(buf, 7 * (f + 8), f + 8, 1, C.byref(out), None) == _lib.TG_ERR_ARG
     assert L.tg_stream_probe(C.c_void_p((1 << 20) + 8), 7 * f, f, 1, C.byref(out),
                              None) == _lib.TG_ERR_ARG
+
+
+def test_forward_static_host_errors():
+    """tg_forward_static rejects null arguments and plans whose workspace
+    exceeds the static scratch on the host, before it looks up the scratch
+    or launches anything."""
+    L = _lib.lib()
+    one = C.c_void_p(8)
+    st, h = create(n=16, nt=4)
+    assert st == _lib.TG_OK
+    assert L.tg_forward_static(h, None, one, one, one, one, None) == _lib.TG_ERR_ARG
+    assert L.tg_forward_static(h, one, one, one, one, None, None) == _lib.TG_ERR_ARG
+    assert L.tg_forward_static(None, one, one, one, one, one, None) == _lib.TG_ERR_ARG
+    L.tg_plan_destroy(h)
+    # 64^3 FP64 keeping every state: about 91 MiB of workspace
+    st, big = create(n=64, nt=16, ckpt_stride=0)
+    assert st == _lib.TG_OK
+    nb = C.c_size_t()
+    assert L.tg_plan_workspace_bytes(big, C.byref(nb)) == _lib.TG_OK
+    assert nb.value > 64 << 20
+    assert L.tg_forward_static(big, one, one, one, one, one, None) == _lib.TG_ERR_SCRATCH_LIMIT
+    assert b"static scratch" in L.tg_status_string(_lib.TG_ERR_SCRATCH_LIMIT)
+    L.tg_plan_destroy(big)
