@@ -18,6 +18,34 @@ forms on trigonometric polynomials and by the dense 8^3 construction.
 from __future__ import annotations
 
 import numpy as np
+import scipy.fft
+
+# Transform library: numpy.fft by default; set_fft_workers(k) switches every
+# transform of this module to scipy.fft (the same pocketfft algorithm) on k
+# threads, for the large grids.  Results agree to rounding.
+_WORKERS = None
+
+
+def set_fft_workers(k):
+    """k >= 1: scipy.fft with k threads; None: numpy.fft (the default)."""
+    global _WORKERS
+    _WORKERS = None if k is None else int(k)
+
+
+def fft_workers():
+    return _WORKERS
+
+
+def rfftn(u):
+    if _WORKERS is None:
+        return np.fft.rfftn(u)
+    return scipy.fft.rfftn(u, workers=_WORKERS)
+
+
+def irfftn(uh, shape):
+    if _WORKERS is None:
+        return np.fft.irfftn(uh, s=shape, axes=(0, 1, 2))
+    return scipy.fft.irfftn(uh, s=shape, axes=(0, 1, 2), workers=_WORKERS)
 
 
 def wavenumbers(n: int):
@@ -43,17 +71,18 @@ def _symbols(n: int):
 def grad(u: np.ndarray) -> list[np.ndarray]:
     """Spectral gradient (D_x u, D_y u, D_z u), D_j u = F^-1(i w_j F u)."""
     n = u.shape[0]
-    uh = np.fft.rfftn(u)
-    return [np.fft.irfftn(1j * s * uh, s=u.shape, axes=(0, 1, 2)) for s in _symbols(n)]
+    uh = rfftn(u)
+    return [irfftn(1j * s * uh, u.shape) for s in _symbols(n)]
 
 
 def div(v: list[np.ndarray]) -> np.ndarray:
     """Spectral divergence sum_j D_j v_j."""
     n = v[0].shape[0]
-    out = np.zeros(np.fft.rfftn(v[0]).shape, dtype=np.complex128)
+    out = None
     for s, vj in zip(_symbols(n), v):
-        out += 1j * s * np.fft.rfftn(vj)
-    return np.fft.irfftn(out, s=v[0].shape, axes=(0, 1, 2))
+        term = 1j * s * rfftn(vj)
+        out = term if out is None else out + term
+    return irfftn(out, v[0].shape)
 
 
 def diffusion(u: np.ndarray, k: np.ndarray) -> np.ndarray:
@@ -71,4 +100,4 @@ def precond_symbol(n: int, dt: float, kbar: float) -> np.ndarray:
 
 
 def apply_precond(r: np.ndarray, sym: np.ndarray) -> np.ndarray:
-    return np.fft.irfftn(sym * np.fft.rfftn(r), s=r.shape, axes=(0, 1, 2))
+    return irfftn(sym * rfftn(r), r.shape)

@@ -4,9 +4,12 @@ generators).
 
     python tests/golden/make_golden.py config2      # 128^3 gradient
     python tests/golden/make_golden.py config3fwd   # 256^3 forward, sampled
+    python tests/golden/make_golden.py config3grad  # 256^3 gradient + 2 GN products
 
 Outputs are small .npz files next to this script: scalars, the full
-gradient vector and c(T) at a seeded sample of grid points.
+gradient vector and c(T) at a seeded sample of grid points.  The 256^3
+runs switch the oracle's transforms to scipy.fft on several threads
+(TG_ORACLE_FFT_WORKERS, default 6); they take a few hours.
 """
 import os
 import sys
@@ -68,6 +71,54 @@ def config3fwd(rtol=1e-10):
                         rho_f=pr.rho_f, k_f=pr.k_f, rtol=rtol, idx=idx, cT=c.ravel()[idx],
                         cT_norm=np.linalg.norm(c), cT_sum=c.sum(), its=np.array(its))
     print(f"config3fwd done in {time.time() - t0:.0f} s", flush=True)
+
+
+def _log(t0, msg):
+    print(f"[{time.time() - t0:7.0f} s] {msg}", flush=True)
+
+
+def config3grad(rtol=1e-10):
+    """256^3 gradient of the benchmark problem (seed 0, 64 Gaussians, rho_f
+    and k_f drawn from the seed, T = 1, nt = 32), then the Gauss-Newton
+    products of the first two of the eight benchmark directions about the
+    same trajectory.  The observation is the oracle's own threshold of the
+    perturbed-p run, stored bit-packed so the GPU tests and the benchmark
+    evaluate exactly this misfit.  Two files: config3_256_grad.npz (written
+    first) and config5_256_hvp.npz."""
+    from oracle import spectral
+    spectral.set_fft_workers(int(os.environ.get("TG_ORACLE_FFT_WORKERS", "6")))
+    n, nt, seed = 256, 32, 0
+    pr = inputs.problem(n, 4, seed, nt=nt)
+    su = tumor.Setup(pr.m, pr.centres, pr.sigma, pr.rho_f, pr.k_f, nt, rtol=rtol)
+    t0 = time.time()
+    _log(t0, f"config3grad: rho_f={pr.rho_f:.6f} k_f={pr.k_f:.6f} rtol={rtol}")
+    tr_obs = tumor.forward(su, inputs.perturbed_p(pr.p, seed))
+    d = inputs.threshold_mask(tr_obs.c[-1])
+    its_obs = list(tr_obs.its)
+    del tr_obs
+    _log(t0, f"observation: {int(d.sum())} voxels, {sum(its_obs)} its")
+    tr = tumor.forward(su, pr.p)
+    _log(t0, f"forward: {sum(tr.its)} its")
+    J, lamT = tumor.misfit(su, tr.c[-1], d)
+    g = tumor.vjp(su, tr, lamT)
+    _log(t0, f"adjoint: {sum(g.its)} its, J={J:.10e}")
+    idx = sample_idx(n)
+    np.savez_compressed(os.path.join(HERE, "config3_256_grad.npz"), n=n, nt=nt, seed=seed,
+                        rho_f=pr.rho_f, k_f=pr.k_f, rtol=rtol, J=J, g_p=g.g_p,
+                        g_rho=g.g_rho, g_k=g.g_k, idx=idx, cT=tr.c[-1].ravel()[idx],
+                        cT_norm=np.linalg.norm(tr.c[-1]), d_bits=np.packbits(d.ravel() > 0),
+                        its_obs=np.array(its_obs), its_fwd=np.array(tr.its),
+                        its_adj=np.array(g.its))
+    del g, lamT
+    V = inputs.hvp_directions(8, pr.p.size, 0)[:2]
+    HV = []
+    for i, v in enumerate(V):
+        HV.append(tumor.gn_hvp(su, tr, v))
+        _log(t0, f"GN product {i}: |Hv| = {np.linalg.norm(HV[-1]):.6e}")
+    np.savez_compressed(os.path.join(HERE, "config5_256_hvp.npz"), n=n, nt=nt, seed=seed,
+                        rho_f=pr.rho_f, k_f=pr.k_f, rtol=rtol, dir_seed=0, V=V,
+                        HV=np.array(HV))
+    _log(t0, "config3grad done")
 
 
 if __name__ == "__main__":
