@@ -44,6 +44,12 @@
  *     anything is launched.  A PCG that hits pcg_maxit, breaks down or
  *     produces non-finite values still writes all outputs and the call
  *     returns TG_ERR_NOT_CONVERGED / TG_ERR_NUMERIC.
+ *   - The growth parameters rho_f and k_f are device values, so they are
+ *     checked on the device: k_f < 0 (anti-diffusion, outside the model)
+ *     or a non-finite k_f or rho_f sets status bit 8 (tg_stats) for that
+ *     problem, its Crank-Nicolson solves are skipped, its outputs are
+ *     meaningless, and the call, and every later call on the same
+ *     trajectory, returns TG_ERR_ARG.
  *   - One plan is used by one stream at a time.
  */
 #ifndef TUMORGRAD_H
@@ -82,10 +88,14 @@ typedef struct tg_desc {
                             copied at tg_plan_bind */
   double sigma;          /* Gaussian standard deviation, > 0 */
   double pcg_rtol;       /* PCG stop: ||r|| <= rtol ||rhs||, 0 < rtol < 1.
-                            TG_FP32_MIXED stops no lower than a floor,
-                            50 eps_32 = 6e-6 unless the environment variable
-                            TUMORGRAD_FP32_RTOL_FLOOR (read when the plan is
-                            bound) sets another value. */
+                            TG_FP32_MIXED stops no lower than a floor: the
+                            adjoint solves at 50 eps_32 = 6.0e-6, the
+                            forward-type solves (forward, segment recompute,
+                            Gauss-Newton tangent) at 16 eps_32 = 1.9e-6.  The
+                            environment variable TUMORGRAD_FP32_RTOL_FLOOR
+                            (read when the plan is bound) sets both floors,
+                            TUMORGRAD_FP32_FWD_RTOL_FLOOR then the forward
+                            one. */
   int pcg_maxit;         /* >= 1 */
   int ckpt_stride;       /* 0: keep every step's state; s > 0: keep every
                             s-th state and recompute segments in the adjoint */
@@ -98,7 +108,9 @@ typedef struct tg_solve_stats {
   int solves;               /* CN solves in the last call */
   int pcg_its_total;        /* PCG iterations summed over those solves */
   int pcg_its_max;          /* largest iteration count of one solve */
-  int status_bits;          /* 1: maxit reached, 2: breakdown, 4: non-finite */
+  int status_bits;          /* 1: maxit reached, 2: breakdown, 4: non-finite,
+                               8: invalid parameter (k_f < 0, or k_f or rho_f
+                               not finite) */
   double worst_rel_residual;/* max over solves of final ||r|| / ||rhs|| */
 } tg_solve_stats;
 
@@ -195,12 +207,17 @@ tg_status tg_vjp(tg_plan* plan, const void* d_lamT, double* d_gp, double* d_grho
  * so sum_x m_diff q_diff = k_f g_kf and sum_x m_react q_react = rho_f g_rho.
  * For tissue maps m_i with k = k_f sum_i k_i m_i and rho = rho_f sum_i
  * rho_i m_i, dJ/dm_i = k_i q_diff + rho_i q_react.  d_q_diff, d_q_react:
- * [B][n^3] in the plan's precision, overwritten; either may be NULL.  The
- * diffusion part adds five transform passes per reverse step (the
- * gradient rows of mu and of s and one z pass that multiplies them).
- * Errors as tg_vjp. */
+ * [B][n^3] in the plan's precision, overwritten; either may be NULL.
+ * combine = 1: d_q_diff receives q_diff + q_react, the derivative in m
+ * when one field drives both coefficients (tg_forward), and d_q_react must
+ * be NULL; combine = 0: the two fields separately.  The diffusion part adds
+ * five transform passes per reverse step (the gradient rows of mu and of s
+ * and one z pass that multiplies them).  Errors as tg_vjp; TG_ERR_ARG for
+ * combine outside {0, 1} or, with combine = 1, a NULL d_q_diff or a
+ * non-NULL d_q_react. */
 tg_status tg_vjp_coupling(tg_plan* plan, const void* d_lamT, double* d_gp, double* d_grho,
-                          double* d_gkf, void* d_q_diff, void* d_q_react, void* stream);
+                          double* d_gkf, void* d_q_diff, void* d_q_react, int combine,
+                          void* stream);
 
 /* Misfit J = 1/2 h^3 sum (c(T) - c_obs)^2 (tumor misfit of Tab. 1) and its
  * gradient: tg_vjp with lamT = h^3 (c(T) - c_obs).  Writes d_J [B]. */

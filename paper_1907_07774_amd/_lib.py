@@ -83,7 +83,7 @@ def lib():
     L.tg_vjp.argtypes = [vp, vp, vp, vp, vp, vp]
     L.tg_adjoint_misfit.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.tg_forward_fields.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
-    L.tg_vjp_coupling.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    L.tg_vjp_coupling.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.c_int, vp]
     L.tg_transport_workspace_bytes.argtypes = [vp, C.c_int, C.c_int, C.POINTER(sz)]
     L.tg_transport.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp, vp, vp, sz, vp]
     L.tg_transport_adjoint.argtypes = [vp, vp, vp, vp, vp]

@@ -149,10 +149,12 @@ class Plan:
         _lib.check(st, "tg_forward")
         return self._shape(cT)
 
-    def vjp(self, lamT, coupling: bool = False):
+    def vjp(self, lamT, coupling: bool = False, combine: bool = False):
         """(g_p, g_rho, g_kf) = d<lamT, c(T)>/d(p, rho_f, k_f) of the last
         forward.  coupling=True adds (q_diff, q_react): the derivatives at
-        every grid point in the diffusion and reaction fields."""
+        every grid point in the diffusion and reaction fields; with
+        combine=True the library returns their sum q_diff + q_react as one
+        field instead (the derivative in m when m drives both)."""
         self._bind()
         lam = self._field(lamT, "lamT")
         gp = torch.empty(self.batch * self.n_p, dtype=torch.float64, device=self.device)
@@ -162,10 +164,14 @@ class Plan:
             _lib.check(_lib.lib().tg_vjp(self._h, _ptr(lam), _ptr(gp), _ptr(gr), _ptr(gk),
                                          self._stream()), "tg_vjp")
             return self._vecs(gp, gr, gk)
-        qd, qr = torch.empty_like(lam), torch.empty_like(lam)
+        qd = torch.empty_like(lam)
+        qr = None if combine else torch.empty_like(lam)
         _lib.check(_lib.lib().tg_vjp_coupling(self._h, _ptr(lam), _ptr(gp), _ptr(gr), _ptr(gk),
-                                              _ptr(qd), _ptr(qr), self._stream()),
+                                              _ptr(qd), _ptr(qr), 1 if combine else 0,
+                                              self._stream()),
                    "tg_vjp_coupling")
+        if combine:
+            return (*self._vecs(gp, gr, gk), self._shape(qd))
         return (*self._vecs(gp, gr, gk), self._shape(qd), self._shape(qr))
 
     def adjoint_misfit(self, c_obs, labels=None):
@@ -357,9 +363,9 @@ class TumorSolve(torch.autograd.Function):
         p, rho, kf, m = ctx.saved_tensors
         gm = None
         if ctx.needs_input_grad[3]:
-            # m drives both coefficients: dJ/dm = q_diff + q_react
-            gp, gr, gk, qd, qr = plan.vjp(grad_cT.detach(), coupling=True)
-            gm = (qd + qr).reshape(m.shape).to(m.dtype)
+            # m drives both coefficients: the library returns dJ/dm = q_diff + q_react
+            gp, gr, gk, q = plan.vjp(grad_cT.detach(), coupling=True, combine=True)
+            gm = q.reshape(m.shape).to(m.dtype)
         else:
             gp, gr, gk = plan.vjp(grad_cT.detach())
         return (gp.view_as(p).to(p.dtype), gr.reshape(rho.shape).to(rho.dtype),
@@ -474,8 +480,22 @@ class BatchGraph:
                    "tg_batch_launch")
         cur.wait_stream(self.stream)
 
-    def results(self):
-        """[(J, g_p, g_rho, g_kf)] per plan (device tensors, batched)."""
+    def results(self, check: bool = True):
+        """[(J, g_p, g_rho, g_kf)] per plan (device tensors, batched).
+
+        check (default): read each plan's solve statistics after the replay
+        and raise if a solve hit its captured iteration budget or pcg_maxit
+        (TG_ERR_NOT_CONVERGED), broke down or went non-finite
+        (TG_ERR_NUMERIC), or met an invalid k_f / rho_f (TG_ERR_ARG): a
+        replay whose inputs need more iterations than the budget otherwise
+        returns unconverged gradients.  Synchronizes the plans' stream."""
+        if check:
+            for i, pl in enumerate(self.plans):
+                bits = pl.stats().status_bits
+                if bits:
+                    st = (_lib.TG_ERR_ARG if bits & 8 else
+                          _lib.TG_ERR_NUMERIC if bits & 6 else _lib.TG_ERR_NOT_CONVERGED)
+                    _lib.check(st, f"BatchGraph plan {i} (status bits {bits})")
         out = []
         for pl, b in zip(self.plans, self._bufs):
             out.append((b["J"], b["gp"].view(pl.batch, pl.n_p), b["grho"], b["gkf"]))

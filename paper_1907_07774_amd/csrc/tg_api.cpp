@@ -72,6 +72,7 @@ size_t layout(const tg_plan& p, char* base, tg::Workspace* w) {
 tg_status from_hip(hipError_t e) { return e == hipSuccess ? TG_OK : TG_ERR_HIP; }
 
 tg_status from_bits(int bits) {
+  if (bits & tg::STAT_BAD_PARAM) return TG_ERR_ARG;
   if (bits & (tg::STAT_BREAKDOWN | tg::STAT_NONFINITE)) return TG_ERR_NUMERIC;
   if (bits & tg::STAT_NOT_CONVERGED) return TG_ERR_NOT_CONVERGED;
   return TG_OK;
@@ -237,10 +238,18 @@ tg_status tg_vjp(tg_plan* plan, const void* d_lamT, double* d_gp, double* d_grho
 }
 
 tg_status tg_vjp_coupling(tg_plan* plan, const void* d_lamT, double* d_gp, double* d_grho,
-                          double* d_gkf, void* d_q_diff, void* d_q_react, void* stream) {
+                          double* d_gkf, void* d_q_diff, void* d_q_react, int combine,
+                          void* stream) {
   if (plan == nullptr || d_lamT == nullptr || d_gp == nullptr || d_grho == nullptr ||
       d_gkf == nullptr)
     return TG_ERR_ARG;
+  if (combine != 0 && combine != 1) return TG_ERR_ARG;
+  if (combine == 1) {
+    // one field receives both parts: the reaction and diffusion kernels each
+    // add into it in turn on the same stream
+    if (d_q_diff == nullptr || d_q_react != nullptr) return TG_ERR_ARG;
+    d_q_react = d_q_diff;
+  }
   if (!plan->have_traj) return TG_ERR_STATE;
   if (!plan->solver) return TG_ERR_WORKSPACE;
   plan->last_stream = (hipStream_t)stream;

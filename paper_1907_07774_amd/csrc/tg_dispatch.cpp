@@ -31,11 +31,7 @@ hipError_t init_twiddles(int fp64, int n) {
   return hipErrorInvalidValue;
 }
 
-// Phi^T partial-sum blocks: n*n/max(64, 256/n) rows (see PhiT in the kernels).
-int phi_blocks_for(int n) {
-  const int rows_t = 256 / n > 0 ? 256 / n : 1;
-  const int rb = 64 > rows_t ? 64 : rows_t;
-  return n * n / rb;
-}
+// Phi^T partial-sum blocks: one per 64 grid rows (PhiTK in the kernels).
+int phi_blocks_for(int n) { return n * n / 64; }
 
 }  // namespace tg

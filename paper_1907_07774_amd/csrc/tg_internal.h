@@ -36,7 +36,9 @@ struct ProbScalars {
   int pad1;
 };
 
-enum : int { STAT_NOT_CONVERGED = 1, STAT_BREAKDOWN = 2, STAT_NONFINITE = 4 };
+// STAT_BAD_PARAM: k_f < 0, or k_f or rho_f not finite (device values, so
+// found by k_init_scalars); every solve of the problem is then skipped.
+enum : int { STAT_NOT_CONVERGED = 1, STAT_BREAKDOWN = 2, STAT_NONFINITE = 4, STAT_BAD_PARAM = 8 };
 
 constexpr int NSLOT = 4;      // simultaneous partial sums per reducing kernel
 constexpr int MAXBLK = 16384;  // max workgroups of a reducing kernel per problem

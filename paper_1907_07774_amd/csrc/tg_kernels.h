@@ -1053,7 +1053,9 @@ k_finalize(ProbScalars* __restrict__ sc, const double* __restrict__ part, int nb
     S.first = 1;
     S.solves += 1;
     S.done = (S.rr <= S.tol2) ? 1 : 0;
-    if (!isfinite(S.rr) || !isfinite(S.rhs2)) {
+    if (S.status & STAT_BAD_PARAM) {
+      S.done = 1;  // invalid k_f / rho_f: no solve
+    } else if (!isfinite(S.rr) || !isfinite(S.rhs2)) {
       S.status |= STAT_NONFINITE;
       S.done = 1;
     }
@@ -1124,6 +1126,7 @@ __global__ void k_init_scalars(ProbScalars* __restrict__ sc, const double* __res
   S.rhof = rho[b * rho_bs];
   S.kf = kf[b * kf_bs];
   S.done = 1;
+  if (!(S.kf >= 0.0) || !isfinite(S.kf) || !isfinite(S.rhof)) S.status = STAT_BAD_PARAM;
   sc[b] = S;
 }
 
@@ -1135,7 +1138,7 @@ __global__ void k_reset_call(ProbScalars* __restrict__ sc, int nb) {
   S.g_rho = 0.0;
   S.g_k = 0.0;
   S.worst = 0.0;
-  S.status = 0;
+  S.status &= STAT_BAD_PARAM;  // a parameter error of the forward stays
   S.its_total = 0;
   S.solves = 0;
   S.its_max = 0;
@@ -1152,6 +1155,7 @@ __global__ void k_copy_dir_scalars(const ProbScalars* __restrict__ src, ProbScal
   S.rhof = src[0].rhof;
   S.kbar = src[0].kbar;
   S.mmax = src[0].mmax;
+  S.status = src[0].status & STAT_BAD_PARAM;
   S.done = 1;
   dst[d] = S;
 }
@@ -1282,17 +1286,32 @@ __global__ void k_basis_factors(const double* __restrict__ centres, long long c_
   g[((size_t)b * n_p + i) * 3 * n + a * n + j] = exp(-d * d / (2.0 * sigma * sigma));
 }
 
-// c0 = w Phi p (w: the CSF mask of Sec. 2.1, or none).  A workgroup takes
-// RB consecutive (x, y) rows, a thread one z and KR of the rows, so each
-// Gaussian's z factor is loaded once per thread and used for KR rows (the
-// x and y factors are uniform over a row).  Every point sums its terms in
-// the order of i, each term formed as ((p_i gx) gy) gz.
+// The basis is separable: Phi_i(x, y, z) = gx_i[x] gy_i[y] gz_i[z] (the
+// rows of k_basis_factors), so both Phi p and Phi^T lam are contractions
+// over the Gaussians i and the z axis of a grid row r = (x, y) with the z
+// factors: [n^2 x n_p] by [n_p x n] and [n^2 x n] by [n x n_p] products.
+// They run as register-tiled products in FP64 (workgroups of 256 threads,
+// 64 rows per workgroup, operands staged through LDS), reading and writing
+// each field once.
+
+// ---- c0 = w Phi p (w: the CSF mask of Sec. 2.1, or none): for each row
+// r = (x, y), c0[r][z] = w sum_i a_i(r) gz_i[z] with a_i(r) = p_i gx_i[x]
+// gy_i[y].  A workgroup computes 64 rows x KZ z values; thread (tr, tz)
+// holds rows tr + TR q (q < RT) and z = tz + TZ a (a < ZT); the Gaussians
+// go through LDS in chunks of 32 (about 34 KB of LDS: four workgroups per
+// CU).
 template <int N>
-struct PhiF {
-  static constexpr int ROWS_T = 256 / N > 0 ? 256 / N : 1;  // rows side by side
-  static constexpr int RB = 16 > ROWS_T ? 16 : ROWS_T;       // rows per block
-  static constexpr int KR = RB / ROWS_T;                     // rows per thread
-  static constexpr int NBLK = N * N / RB;
+struct PhiK {
+  static constexpr int ROWS = 64;                        // rows per workgroup
+  static constexpr int KZ = N < 64 ? N : 64;             // z values per workgroup
+  static constexpr int ZT = KZ >= 64 ? 4 : (KZ >= 32 ? 2 : 1);  // z per thread
+  static constexpr int TZ = KZ / ZT;                     // threads along z
+  static constexpr int TR = 256 / TZ;                    // threads along rows
+  static constexpr int RT = ROWS / TR;                   // rows per thread
+  static constexpr int GC = 32;                          // Gaussians per LDS chunk
+  static constexpr int NBX = N * N / ROWS;               // row blocks
+  static constexpr int NBZ = N / KZ;                     // z blocks
+  static_assert(RT >= 1 && TR * RT == ROWS && TZ * ZT == KZ, "Phi tile shape");
 };
 
 template <typename T, int N>
@@ -1300,43 +1319,92 @@ __global__ void __launch_bounds__(256) k_phi(const double* __restrict__ p, long 
                                              const double* __restrict__ g, long long g_bs,
                                              const T* __restrict__ mask, long long mask_bs,
                                              T* __restrict__ out, long long out_bs, int n_p) {
-  using F = PhiF<N>;
+  using K = PhiK<N>;
+  constexpr int SA = K::ROWS * K::GC / 256, SZ = K::GC * K::KZ / 256;  // staged per thread
+  static_assert(SA * 256 == K::ROWS * K::GC && SZ * 256 == K::GC * K::KZ, "Phi staging");
+  __shared__ double sa[K::ROWS][K::GC + 1];  // a_i(r), rows x Gaussians
+  __shared__ double sz[K::GC][K::KZ + 1];    // gz_i[z], Gaussians x z
   const int b = blockIdx.y;
-  const int z = threadIdx.x % N;
-  const int r0 = threadIdx.x / N;
+  const int t = threadIdx.x, tz = t % K::TZ, tr = t / K::TZ;
+  const long long r0 = (long long)(blockIdx.x % K::NBX) * K::ROWS;
+  const int z0 = (blockIdx.x / K::NBX) * K::KZ;
   const double* gb = g + b * g_bs;
-  int xs[F::KR], ys[F::KR];
-  double acc[F::KR];
+  const double* pb = p + b * p_bs;
+  double acc[K::RT][K::ZT];
 #pragma unroll
-  for (int k = 0; k < F::KR; ++k) {
-    const long long rowid = (long long)blockIdx.x * F::RB + r0 + k * F::ROWS_T;
-    xs[k] = (int)(rowid / N);
-    ys[k] = (int)(rowid % N);
-    acc[k] = 0.0;
+  for (int q = 0; q < K::RT; ++q)
+#pragma unroll
+    for (int a = 0; a < K::ZT; ++a) acc[q][a] = 0.0;
+  // the next chunk's operands are fetched into registers while the current
+  // one is multiplied out of LDS
+  double ra[SA], rz[SZ];
+  auto fetch = [&](int i0) {
+#pragma unroll
+    for (int u = 0; u < SA; ++u) {
+      const int e = t + 256 * u, rr = e / K::GC, i = i0 + e % K::GC;
+      const long long r = r0 + rr;
+      ra[u] = i < n_p ? pb[i] * gb[((size_t)i * 3) * N + r / N] * gb[((size_t)i * 3 + 1) * N + r % N]
+                      : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < SZ; ++u) {
+      const int e = t + 256 * u, i = i0 + e / K::KZ;
+      rz[u] = i < n_p ? gb[((size_t)i * 3 + 2) * N + z0 + e % K::KZ] : 0.0;
+    }
+  };
+  fetch(0);
+  for (int i0 = 0; i0 < n_p; i0 += K::GC) {
+#pragma unroll
+    for (int u = 0; u < SA; ++u) {
+      const int e = t + 256 * u;
+      sa[e / K::GC][e % K::GC] = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < SZ; ++u) {
+      const int e = t + 256 * u;
+      sz[e / K::KZ][e % K::KZ] = rz[u];
+    }
+    __syncthreads();
+    if (i0 + K::GC < n_p) fetch(i0 + K::GC);
+    const int ni = min(K::GC, n_p - i0);
+    for (int ii = 0; ii < ni; ++ii) {
+      double av[K::RT], zv[K::ZT];
+#pragma unroll
+      for (int q = 0; q < K::RT; ++q) av[q] = sa[tr + K::TR * q][ii];
+#pragma unroll
+      for (int a = 0; a < K::ZT; ++a) zv[a] = sz[ii][tz + K::TZ * a];
+#pragma unroll
+      for (int q = 0; q < K::RT; ++q)
+#pragma unroll
+        for (int a = 0; a < K::ZT; ++a) acc[q][a] = fma(av[q], zv[a], acc[q][a]);
+    }
+    __syncthreads();
   }
-  for (int i = 0; i < n_p; ++i) {
-    const double* gi = gb + (size_t)i * 3 * N;
-    const double pi = p[b * p_bs + i];
-    const double gz = gi[2 * N + z];
 #pragma unroll
-    for (int k = 0; k < F::KR; ++k) acc[k] += pi * gi[xs[k]] * gi[N + ys[k]] * gz;
-  }
+  for (int q = 0; q < K::RT; ++q) {
+    const long long o = (r0 + tr + K::TR * q) * N + z0 + tz;
 #pragma unroll
-  for (int k = 0; k < F::KR; ++k) {
-    const long long o = ((long long)blockIdx.x * F::RB + r0 + k * F::ROWS_T) * N + z;
-    double v = acc[k];
-    if (mask) v *= (double)mask[b * mask_bs + o];
-    out[b * out_bs + o] = (T)v;
+    for (int a = 0; a < K::ZT; ++a) {
+      double v = acc[q][a];
+      if (mask) v *= (double)mask[b * mask_bs + o + K::TZ * a];
+      out[b * out_bs + o + K::TZ * a] = (T)v;
+    }
   }
 }
 
-// Partials of Phi^T lam: block = RB rows, thread = z (or several rows);
-// partphi[b][i][blk].
-template <typename T, int N>
-struct PhiT {
-  static constexpr int ROWS_T = 256 / N > 0 ? 256 / N : 1;  // rows handled at once
-  static constexpr int RB = 64 > ROWS_T ? 64 : ROWS_T;       // rows per block
-  static constexpr int NBLK = N * N / RB;
+// ---- Phi^T (w lam): for each row r = (x, y), T_i(r) = sum_z gz_i[z]
+// (w lam)[r][z]; each workgroup of 64 rows then reduces sum_r gx_i[x]
+// gy_i[y] T_i(r) into partphi[b][i][block] (k_phit_final adds the blocks
+// in a fixed order).  Thread (tr, ti) holds rows tr + 16 q and Gaussians
+// ti + 16 a (q, a < 4) of a 64 x 64 tile; z goes through LDS in chunks of
+// KC = 64; grid.z walks the Gaussians in blocks of 64.  lam (times the mask)
+// is read once per Gaussian block.
+template <int N>
+struct PhiTK {
+  static constexpr int ROWS = 64;
+  static constexpr int G = 64;                 // Gaussians per workgroup
+  static constexpr int KC = N < 64 ? N : 64;   // z values per LDS chunk
+  static constexpr int NBLK = N * N / ROWS;    // partial sums per Gaussian
 };
 
 template <typename T, int N>
@@ -1344,30 +1412,89 @@ __global__ void __launch_bounds__(256) k_phit(const T* __restrict__ lam, long lo
                                               const double* __restrict__ g, long long g_bs,
                                               const T* __restrict__ mask, long long mask_bs,
                                               double* __restrict__ partphi, int n_p) {
-  using P = PhiT<T, N>;
-  __shared__ double red[NSLOT * 4];
-  const int b = blockIdx.y;
-  const int z = threadIdx.x % N;
-  const int r0 = threadIdx.x / N;
+  using K = PhiTK<N>;
+  constexpr int SL = K::ROWS * K::KC / 256, SG = K::G * K::KC / 256;  // staged per thread
+  static_assert(SL * 256 == K::ROWS * K::KC && SG * 256 == K::G * K::KC, "Phi^T staging");
+  __shared__ T sl[K::ROWS][K::KC + 1];       // (w lam), rows x z, in its own precision
+  __shared__ double sg[K::G][K::KC + 1];     // gz_i[z], Gaussians x z
+  __shared__ double red[16][K::G];
+  const int b = blockIdx.y, gi0 = blockIdx.z * K::G;
+  const int t = threadIdx.x, ti = t % 16, tr = t / 16;
+  const long long r0 = (long long)blockIdx.x * K::ROWS;
   const double* gb = g + b * g_bs;
   const T* lb = lam + b * lam_bs;
-  for (int i0 = 0; i0 < n_p; i0 += NSLOT) {
-    double acc[NSLOT] = {0.0, 0.0, 0.0, 0.0};
-    const int ni = min(NSLOT, n_p - i0);
-    for (int rr = r0; rr < P::RB; rr += P::ROWS_T) {
-      const long long rowid = (long long)blockIdx.x * P::RB + rr;
-      const int x = (int)(rowid / N), y = (int)(rowid % N);
-      double l = (double)lb[rowid * N + z];
-      if (mask) l *= (double)mask[b * mask_bs + rowid * N + z];
-      for (int q = 0; q < ni; ++q) {
-        const double* gi = gb + (size_t)(i0 + q) * 3 * N;
-        acc[q] += gi[x] * gi[N + y] * gi[2 * N + z] * l;
+  const T* mb = mask ? mask + b * mask_bs : nullptr;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[a][q] = 0.0;
+  // the next z chunk is fetched into registers while the current one is
+  // multiplied out of LDS
+  T rl[SL];
+  double rg[SG];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < SL; ++u) {
+      const int e = t + 256 * u;
+      const long long o = (r0 + e / K::KC) * N + k0 + e % K::KC;
+      T v = lb[o];
+      if (mb) v *= mb[o];
+      rl[u] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < SG; ++u) {
+      const int e = t + 256 * u, i = gi0 + e / K::KC;
+      rg[u] = i < n_p ? gb[((size_t)i * 3 + 2) * N + k0 + e % K::KC] : 0.0;
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < N; k0 += K::KC) {
+#pragma unroll
+    for (int u = 0; u < SL; ++u) {
+      const int e = t + 256 * u;
+      sl[e / K::KC][e % K::KC] = rl[u];
+    }
+#pragma unroll
+    for (int u = 0; u < SG; ++u) {
+      const int e = t + 256 * u;
+      sg[e / K::KC][e % K::KC] = rg[u];
+    }
+    __syncthreads();
+    if (k0 + K::KC < N) fetch(k0 + K::KC);
+    for (int kk = 0; kk < K::KC; ++kk) {
+      double lv[4], gv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) lv[q] = (double)sl[tr + 16 * q][kk];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) gv[a] = sg[ti + 16 * a][kk];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[a][q] = fma(gv[a], lv[q], acc[a][q]);
+    }
+    __syncthreads();
+  }
+  // weight each row by gx_i[x] gy_i[y] and sum this thread's four rows
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int i = gi0 + ti + 16 * a;
+    double s = 0.0;
+    if (i < n_p) {
+      const double* gx = gb + (size_t)i * 3 * N;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const long long r = r0 + tr + 16 * q;
+        s += acc[a][q] * (gx[r / N] * gx[N + r % N]);
       }
     }
-    block_sums<256>(acc, ni, red);
-    if (threadIdx.x == 0)
-      for (int q = 0; q < ni; ++q)
-        partphi[((size_t)b * n_p + i0 + q) * P::NBLK + blockIdx.x] = acc[q];
+    red[tr][ti + 16 * a] = s;
+  }
+  __syncthreads();
+  if (t < K::G && gi0 + t < n_p) {
+    double s = 0.0;
+    for (int k = 0; k < 16; ++k) s += red[k][t];
+    partphi[((size_t)b * n_p + gi0 + t) * K::NBLK + blockIdx.x] = s;
   }
 }
 

@@ -34,7 +34,6 @@ namespace tg {
 template <typename T, int N>
 class Solver final : public ISolver {
   using RPc = RP<T, N>;
-  using PT = PhiT<T, N>;
   static constexpr long long REAL = (long long)N * N * N;
   static constexpr long long SPECN = (long long)N * N * (N / 2);
 
@@ -62,6 +61,15 @@ class Solver final : public ISolver {
     if (const char* f = std::getenv("TUMORGRAD_FP32_RTOL_FLOOR")) {
       const double v = std::atof(f);
       if (v > 0.0 && v < 1.0) fp32_floor_ = v;
+    }
+    // forward-type solves: 16 eps_32 (their error dominates the FP32-mixed
+    // error of the rho_f derivative: at 50 eps_32 it was 1.3e-4 of the
+    // oracle's in the 128^3 gradient, at 16 eps_32 3e-5)
+    fp32_fwd_floor_ = std::getenv("TUMORGRAD_FP32_RTOL_FLOOR") ? fp32_floor_
+                                                               : 16.0 * 1.1920928955078125e-07;
+    if (const char* f = std::getenv("TUMORGRAD_FP32_FWD_RTOL_FLOOR")) {
+      const double v = std::atof(f);
+      if (v > 0.0 && v < 1.0) fp32_fwd_floor_ = v;
     }
   }
 
@@ -151,7 +159,7 @@ class Solver final : public ISolver {
     k_basis_factors<<<dim3((nf + 255) / 256, d_.batch), 256, 0, st_>>>(
         w_.centres, (long long)d_.n_p * 3, w_.gfac, N, d_.n_p, d_.sigma);
     TG_LAUNCH_CHECK();
-    k_phi<T, N><<<dim3(PhiF<N>::NBLK, d_.batch), 256, 0, st_>>>(
+    k_phi<T, N><<<dim3(PhiK<N>::NBX * PhiK<N>::NBZ, d_.batch), 256, 0, st_>>>(
         p, d_.n_p, w_.gfac, (long long)d_.n_p * 3 * N, mask_, REAL, ck(0), REAL, d_.n_p);
     TG_LAUNCH_CHECK();
     TG_CHECK(fwd_steps(c, 0, d_.nt, /*initial=*/true));
@@ -174,7 +182,10 @@ class Solver final : public ISolver {
     TG_LAUNCH_CHECK();
     qk_ = (T*)qk;
     qr_ = (T*)qr;
-    for (T* q : {qk_, qr_}) {
+    // the output fields accumulate over the sweep: clear them first (once
+    // when both parts go to one field)
+    T* const qclr[2] = {qk_, qr_ != qk_ ? qr_ : nullptr};
+    for (T* q : qclr) {
       if (q == nullptr) continue;
       const long long nq = (long long)d_.batch * REAL;
       k_zero<T><<<(int)std::min<long long>((nq + 255) / 256, 8192), 256, 0, st_>>>(q, nq);
@@ -216,7 +227,7 @@ class Solver final : public ISolver {
     k_copy_dir_scalars<<<(ndir + 63) / 64, 64, 0, st_>>>(w_.sc, dc.sc, ndir);
     TG_LAUNCH_CHECK();
     // dc0 = Phi v for each direction
-    k_phi<T, N><<<dim3(PhiF<N>::NBLK, ndir), 256, 0, st_>>>(V, d_.n_p, w_.gfac, 0, mask_, 0,
+    k_phi<T, N><<<dim3(PhiK<N>::NBX * PhiK<N>::NBZ, ndir), 256, 0, st_>>>(V, d_.n_p, w_.gfac, 0, mask_, 0,
                                                           lam(0), REAL, d_.n_p);
     TG_LAUNCH_CHECK();
     // tangent sweep, forward in time
@@ -447,7 +458,7 @@ class Solver final : public ISolver {
       sch_.x_fwd_div(XM_SHIFT, c.T1, c.T2, c.X, c.R, dd, c.sc, c.part, tau_, 0, 0, c.nb, st_);
       TG_LAUNCH_CHECK();
     }
-    k_finalize<FIN_INIT><<<c.nb, 256, 0, st_>>>(c.sc, c.part, sch_.xf_nblk, 1.0 / REAL, rtol(),
+    k_finalize<FIN_INIT><<<c.nb, 256, 0, st_>>>(c.sc, c.part, sch_.xf_nblk, 1.0 / REAL, rtol(adj),
                                                 maxit());
     TG_LAUNCH_CHECK();
     TG_CHECK(pcg_loop(c, est, exact));
@@ -478,10 +489,14 @@ class Solver final : public ISolver {
     if (graph_budget_ == 0) hist_[kind_] = rec_;
   }
 
-  double rtol() const {
-    // FP32 arithmetic cannot certify residuals near its rounding level:
-    // stop at a floor (default 50 eps_32) if rtol asks for less.
-    if (sizeof(T) == 4) return std::max(d_.rtol, fp32_floor_);
+  // Stopping tolerance of a solve (only FIN_INIT uses it: it fixes the
+  // solve's target |r|^2).  FP32 arithmetic cannot certify residuals near
+  // its rounding level: stop at a floor if rtol asks for less, one for the
+  // adjoint solves and one for the forward-type solves (forward, segment
+  // recompute, tangent), whose error is what the rho_f derivative is most
+  // sensitive to.
+  double rtol(bool adj = false) const {
+    if (sizeof(T) == 4) return std::max(d_.rtol, adj ? fp32_floor_ : fp32_fwd_floor_);
     return d_.rtol;
   }
 
@@ -861,8 +876,9 @@ class Solver final : public ISolver {
   // g[b] = Phi^T lam(b)
   hipError_t phit(const Ctx& c, double* out, long long g_bs = -1) {
     if (g_bs < 0) g_bs = (long long)d_.n_p * 3 * N;
-    k_phit<T, N><<<dim3(PT::NBLK, c.nb), 256, 0, st_>>>(lam(0), REAL, w_.gfac, g_bs, mask_,
-                                                        c.m_bs, w_.partphi, d_.n_p);
+    using PT = PhiTK<N>;
+    k_phit<T, N><<<dim3(PT::NBLK, c.nb, (d_.n_p + PT::G - 1) / PT::G), 256, 0, st_>>>(
+        lam(0), REAL, w_.gfac, g_bs, mask_, c.m_bs, w_.partphi, d_.n_p);
     TG_LAUNCH_CHECK();
     k_phit_final<<<dim3(d_.n_p, c.nb), 256, 0, st_>>>(w_.partphi, PT::NBLK, d_.n_p, out, d_.n_p);
     TG_LAUNCH_CHECK();
@@ -896,7 +912,8 @@ class Solver final : public ISolver {
   std::vector<int> rec_;
   int kind_ = 0;
   size_t seq_ = 0;
-  double fp32_floor_ = 0.0;
+  double fp32_floor_ = 0.0;      // FP32 stopping floor of the adjoint solves
+  double fp32_fwd_floor_ = 0.0;  // ... of the forward, recompute and tangent solves
   int its_max_call_ = 0;
   Sched<T, N> sch_;
   int zwaves_ = 0;

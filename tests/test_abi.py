@@ -129,9 +129,14 @@ def test_model_and_coupling_calls_check_on_the_host():
     assert L.tg_forward_fields(h, p, p, p, p, None, None, None, None) == _lib.TG_ERR_ARG
     assert L.tg_forward_fields(h, p, p, p, p, None, None, p, None) == _lib.TG_ERR_WORKSPACE
     assert L.tg_forward_fields(h, p, p, p, p, p, p, p, None) == _lib.TG_ERR_WORKSPACE
-    assert L.tg_vjp_coupling(h, p, p, p, p, p, p, None) == _lib.TG_ERR_STATE
-    assert L.tg_vjp_coupling(h, None, p, p, p, p, p, None) == _lib.TG_ERR_ARG
-    assert L.tg_vjp_coupling(h, p, p, p, None, p, p, None) == _lib.TG_ERR_ARG
+    assert L.tg_vjp_coupling(h, p, p, p, p, p, p, 0, None) == _lib.TG_ERR_STATE
+    assert L.tg_vjp_coupling(h, p, p, p, p, p, None, 1, None) == _lib.TG_ERR_STATE
+    assert L.tg_vjp_coupling(h, None, p, p, p, p, p, 0, None) == _lib.TG_ERR_ARG
+    assert L.tg_vjp_coupling(h, p, p, p, None, p, p, 0, None) == _lib.TG_ERR_ARG
+    # combine = 1 takes one output field: d_q_diff set, d_q_react NULL
+    assert L.tg_vjp_coupling(h, p, p, p, p, p, p, 1, None) == _lib.TG_ERR_ARG
+    assert L.tg_vjp_coupling(h, p, p, p, p, None, None, 1, None) == _lib.TG_ERR_ARG
+    assert L.tg_vjp_coupling(h, p, p, p, p, p, p, 2, None) == _lib.TG_ERR_ARG
     assert L.tg_adjoint_misfit_labels(h, p, 0, None, None, p, p, p, p, None) == _lib.TG_ERR_STATE
     assert L.tg_adjoint_misfit_labels(h, p, 3, p, p, p, p, p, p, None) == _lib.TG_ERR_STATE
     assert L.tg_adjoint_misfit_labels(h, p, -1, p, p, p, p, p, p, None) == _lib.TG_ERR_ARG

@@ -64,9 +64,11 @@ def config2_problem(g):
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
 def test_config2_gradient_128(prec, tol):
-    """The scalar derivatives are sums with cancellation (here |g_rho| is
-    ~1e-3 J / rho_f), so FP32 is held to tol on the log-sensitivity:
-    |theta| |dg| <= tol (|theta g| + J); FP64 to tol relative."""
+    """Every result within tol relative of the oracle (vector relative L2
+    for c(T) samples and g_p).  Measured FP32-mixed errors: J 2e-7, g_p
+    9e-6, g_rho 3e-5, g_k 2e-7; g_rho is a sum with about six-fold
+    cancellation whose error follows the forward solves' stopping floor
+    (1.3e-4 with the forward floor at 50 eps_32 instead of 16 eps_32)."""
     print(f"case config2 {prec}", flush=True)
     g = load_golden("config2_128.npz")
     pr, d = config2_problem(g)
@@ -77,10 +79,8 @@ def test_config2_gradient_128(prec, tol):
     assert np.linalg.norm(cT[g["idx"]] - g["cT"]) / np.linalg.norm(g["cT"]) < tol
     assert abs(float(J) - float(g["J"])) < tol * abs(float(g["J"]))
     assert rel(gp.cpu().numpy(), g["g_p"]) < tol
-    for got, ref, theta in ((gr, g["g_rho"], g["rho_f"]), (gk, g["g_k"], g["k_f"])):
-        ref, theta = float(ref), abs(float(theta))
-        scale = abs(ref) if prec == "fp64" else abs(ref) + float(g["J"]) / theta
-        assert abs(float(got) - ref) < tol * scale
+    for got, ref in ((gr, g["g_rho"]), (gk, g["g_k"])):
+        assert abs(float(got) - float(ref)) < tol * abs(float(ref))
 
 
 def test_config2_central_fd_128():

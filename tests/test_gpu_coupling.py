@@ -50,6 +50,11 @@ def test_coupling_fields_fp64(n, nt, ckpt):
     # the plain vjp after it is unchanged (the coupling outputs are off again)
     gp2, gr2, gk2 = plan.vjp(lam)
     assert np.array_equal(gp2.cpu().numpy(), gp.cpu().numpy()) and float(gk2) == float(gk)
+    # combine = 1: the library sums both parts into one field (the derivative
+    # in m when m drives both coefficients), against the oracle's sum
+    gp3, gr3, gk3, q = plan.vjp(lam, coupling=True, combine=True)
+    assert rel(q.cpu().numpy(), g.g_mdiff + g.g_mreact) < 1e-10
+    assert np.array_equal(gp3.cpu().numpy(), gp.cpu().numpy()) and float(gk3) == float(gk)
 
 
 def test_coupling_fields_full_model_fp64():

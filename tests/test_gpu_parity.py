@@ -211,6 +211,38 @@ def test_nan_input_reports_numeric():
     assert ei.value.status == _lib.TG_ERR_NUMERIC
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_invalid_growth_parameters_report_arg_error(prec):
+    """k_f < 0 and non-finite k_f or rho_f are device values: the forward
+    sets status bit 8, skips the problem's solves and returns TG_ERR_ARG,
+    and so does the adjoint of that trajectory; a valid forward on the same
+    plan afterwards clears it and matches a fresh plan bit for bit."""
+    print(f"case invalid parameters {prec}", flush=True)
+    pr, p = case(16, 2, 14, 2, 5.0, 0.3)
+    plan = api.Plan(16, 2, pr.centres, pr.sigma, rtol=1e-10, precision=prec)
+    d = inputs.random_field(16, 14)
+    for rho, kf in ((pr.rho_f, -0.1), (pr.rho_f, float("nan")), (float("inf"), pr.k_f),
+                    (pr.rho_f, float("-inf"))):
+        with pytest.raises(_lib.TumorGradError) as ei:
+            plan.forward(p, rho, kf, pr.m)
+        assert ei.value.status == _lib.TG_ERR_ARG
+        st = plan.stats()
+        assert st.status_bits & 8 and st.pcg_its_total == 0
+        with pytest.raises(_lib.TumorGradError) as ei:
+            plan.adjoint_misfit(d)
+        assert ei.value.status == _lib.TG_ERR_ARG
+    cT = plan.forward(p, pr.rho_f, pr.k_f, pr.m).cpu().numpy()
+    J, gp, gr, gk = plan.adjoint_misfit(d)
+    assert plan.stats().status_bits == 0
+    fresh = api.Plan(16, 2, pr.centres, pr.sigma, rtol=1e-10, precision=prec)
+    assert np.array_equal(fresh.forward(p, pr.rho_f, pr.k_f, pr.m).cpu().numpy(), cT)
+    J1, gp1, gr1, gk1 = fresh.adjoint_misfit(d)
+    assert float(J1) == float(J) and np.array_equal(gp1.cpu().numpy(), gp.cpu().numpy())
+    # k_f = 0 is valid (reaction only)
+    plan.forward(p, pr.rho_f, 0.0, pr.m)
+    assert plan.stats().status_bits == 0
+
+
 def test_vjp_before_forward_is_state_error():
     pr, p = case(16, 2, 12, 2, 5.0, 0.3)
     plan = gpu_plan(pr)
@@ -277,3 +309,26 @@ def test_batch_graph_replays_match_eager():
         torch.cuda.synchronize()
     for pl in bg.plans:
         assert pl.stats().status_bits == 0
+
+
+def test_batch_graph_budget_overrun_is_an_error():
+    """A graph captured with a PCG budget too small for its solves: the
+    replay runs to the end (every kernel of a stopped solve returns at
+    once), and results() raises TG_ERR_NOT_CONVERGED instead of handing
+    out unconverged gradients; results(check=False) still returns them."""
+    print("case batch_graph budget overrun", flush=True)
+    probs = [case(16, 2, 70 + s, 4, 6.0, 0.3) for s in range(2)]
+    prs = [q[0] for q in probs]
+    plan = api.Plan(16, 4, np.stack([q.centres for q in prs]), prs[0].sigma, rtol=1e-10,
+                    batch=2, precision="fp32")
+    item = (plan, np.stack([q[1] for q in probs]), [q.rho_f for q in prs],
+            [q.k_f for q in prs], np.stack([q.m for q in prs]),
+            np.stack([inputs.random_field(16, 70 + s) for s in range(2)]))
+    bg = api.BatchGraph([item], pcg_budget=2)
+    bg.launch()
+    torch.cuda.synchronize()
+    with pytest.raises(_lib.TumorGradError) as ei:
+        bg.results()
+    assert ei.value.status == _lib.TG_ERR_NOT_CONVERGED
+    J, gp, gr, gk = bg.results(check=False)[0]
+    assert torch.isfinite(J).all() and torch.isfinite(gp).all()
