@@ -48,6 +48,9 @@ def parse():
     ap.add_argument("--no-equal-accuracy", action="store_true",
                     help="skip the FP64 runs that match the FP32-mixed gradient accuracy")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="only time whole FP64 oracle gradients at 64^3 and 128^3 on this "
+                         "host (no GPU) and print them as JSON")
     ap.add_argument("--timer-kernel", default="z_matvec", choices=sorted(KERNEL_FIELDS))
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
@@ -173,6 +176,22 @@ def run_precision(torch, api, inputs, pr, c_obs, precision, args, steps, warmup,
     return res
 
 
+def load_oracle_gradient(np, args, pr):
+    """The FP64 oracle's gradient of exactly this workload (observation
+    included), stored by tests/golden/make_golden.py, or None."""
+    path = os.path.join(ROOT, "tests", "golden", "config3_256_grad.npz")
+    if not os.path.exists(path):
+        return None
+    g = np.load(path)
+    if (int(g["n"]), int(g["nt"]), int(g["seed"])) != (args.n, args.nt, args.seed) or \
+            g["g_p"].size != pr.p.size or args.g != 4:
+        return None
+    d = np.unpackbits(g["d_bits"])[:args.n ** 3].astype(np.float64)
+    return {"J": float(g["J"]), "gp": np.asarray(g["g_p"]), "g_rho": float(g["g_rho"]),
+            "g_kf": float(g["g_k"]), "rtol": float(g["rtol"]),
+            "d": d.reshape(args.n, args.n, args.n)}
+
+
 def rel_errors(np, a, ref):
     """Relative errors of a run's results against a reference run."""
     out = {"J": abs(a["J"] - ref["J"]) / abs(ref["J"]),
@@ -184,14 +203,20 @@ def rel_errors(np, a, ref):
     return out
 
 
-def equal_accuracy(torch, np, api, inputs, pr, c_obs, args, r32):
+def equal_accuracy(torch, np, api, inputs, pr, c_obs, args, r32, oracle=None):
     """FP32-mixed against FP64 at equal gradient accuracy.  Reference: the
-    FP64 path at rtol 1e-11 (itself within 1e-10 of the FP64 oracle).  The
-    FP64 path is then run at growing accuracy (rtol 1e-5 .. 1e-7) until its
-    g_p error is at most the FP32-mixed one; that run is timed again after a
-    warm-up and compared with the FP32-mixed time per gradient."""
-    ref = run_precision(torch, api, inputs, pr, c_obs, "fp64", args, 1, 0, None, rtol=1e-11,
-                        keep_state=True)
+    FP64 oracle's gradient of this workload (stored, oracle PCG rtol 1e-10)
+    when there is one, else the FP64 path at rtol 1e-11.  The FP64 path is
+    run at growing accuracy (rtol 1e-5 .. 1e-7) until its g_p error is at
+    most the FP32-mixed one; that run is timed again after a warm-up and
+    compared with the FP32-mixed time per gradient."""
+    if oracle is not None:
+        ref = oracle
+        ref_name = f"FP64 oracle (CPU), PCG rtol {oracle['rtol']:g}"
+    else:
+        ref = run_precision(torch, api, inputs, pr, c_obs, "fp64", args, 1, 0, None,
+                            rtol=1e-11, keep_state=True)
+        ref_name = "FP64 path at PCG rtol 1e-11"
     e32 = rel_errors(np, r32, ref)
     ladder = []
     chosen = None
@@ -203,7 +228,7 @@ def equal_accuracy(torch, np, api, inputs, pr, c_obs, args, r32):
         if e["g_p"] <= e32["g_p"]:
             chosen = (rt, e)
             break
-    res = {"reference": "FP64 path at PCG rtol 1e-11", "fp32_mixed_err": e32,
+    res = {"reference": ref_name, "fp32_mixed_err": e32,
            "fp32_mixed_s": r32["ms_per_step"] / 1000.0, "fp64_ladder": ladder}
     if chosen is not None:
         rt, e = chosen
@@ -541,10 +566,33 @@ def transport_workload(torch, np, api, inputs, args):
     return out
 
 
+def host_cpu():
+    """(model name, logical CPUs, CPUs this process may run on)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = os.cpu_count() or 1
+    return model, os.cpu_count() or 1, avail
+
+
 def cpu_baseline(pr, res32):
-    """Time the FP64 oracle's per-iteration work at the same size (operator
-    and preconditioner applications), scaled by the PCG work of one
-    gradient as counted on the GPU run."""
+    """CPU baseline leg: the FP64 oracle on this host.  One application each
+    of its Crank-Nicolson operator and Fourier preconditioner at the
+    benchmark's size, on one thread (numpy.fft) and on every core this
+    process may use (scipy.fft workers), each scaled by one gradient's PCG
+    work as counted on the GPU run (a whole oracle gradient at 256^3 takes
+    hours).  Whole oracle gradients at 64^3 and 128^3, measured by
+    `bench.py --cpu-full` on a GPU machine's host, are attached from
+    profiles/cpu_oracle_gradients.json."""
     import numpy as np
     from oracle import spectral
     n = pr.n
@@ -552,33 +600,86 @@ def cpu_baseline(pr, res32):
     k = pr.k_f * pr.m
     sym = spectral.precond_symbol(n, dt, pr.k_f * float(pr.m.max()))
     u = np.array(pr.m, copy=True)
-    reps = 2
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        v = u - 0.5 * dt * spectral.diffusion(u, k)
-    t_mv = (time.perf_counter() - t0) / reps
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        w = spectral.apply_precond(v, sym)
-    t_pc = (time.perf_counter() - t0) / reps
+    model, ncpu, avail = host_cpu()
     its = res32["pcg_its_forward"] + res32["pcg_its_adjoint"]
     solves = res32["solves_forward"] + res32["solves_adjoint"]
-    adj_solves = pr.nt
-    mv_count = its + solves + adj_solves
-    t_grad = its * t_pc + mv_count * t_mv
-    del w
-    return {
-        "value": 1.0 / t_grad, "unit": "gradient evals/s", "cores": 1, "kind": "oracle",
-        "sample": (f"{reps} applications each of the FP64 oracle's Crank-Nicolson operator "
-                   f"({t_mv:.2f} s) and Fourier preconditioner ({t_pc:.2f} s) at {n}^3 "
-                   f"(numpy pocketfft, 1 thread), scaled by one gradient's PCG work on the GPU "
-                   f"run: {its} iterations, {mv_count} operator applications"),
-        "seconds_per_gradient": t_grad,
+    mv_count = its + solves + pr.nt
+    per = {}
+    for label, workers in (("1_thread", None), ("all_cores", avail)):
+        spectral.set_fft_workers(workers)
+        t0 = time.perf_counter()
+        v = u - 0.5 * dt * spectral.diffusion(u, k)
+        t_mv = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        w = spectral.apply_precond(v, sym)
+        t_pc = time.perf_counter() - t0
+        per[label] = {"threads": workers or 1, "operator_s": t_mv, "precond_s": t_pc,
+                      "seconds_per_gradient": its * t_pc + mv_count * t_mv}
+        del v, w
+    spectral.set_fft_workers(None)
+    best = per["all_cores"]
+    out = {
+        "value": 1.0 / best["seconds_per_gradient"], "unit": "gradient evals/s",
+        "cores": best["threads"], "kind": "oracle",
+        "sample": (f"one application each of the FP64 oracle's Crank-Nicolson operator and "
+                   f"Fourier preconditioner at {n}^3 on {best['threads']} threads (scipy.fft "
+                   f"workers; elementwise numpy work on one), scaled by one gradient's PCG "
+                   f"work on the GPU run: {its} preconditioner and {mv_count} operator "
+                   f"applications"),
+        "seconds_per_gradient": best["seconds_per_gradient"],
+        "host_cpu": {"model": model, "logical_cpus": ncpu, "available_cpus": avail},
+        "per_thread_count": per,
     }
+    path = os.path.join(ROOT, "profiles", "cpu_oracle_gradients.json")
+    try:
+        with open(path) as fh:
+            out["whole_gradients"] = json.load(fh)
+    except (OSError, ValueError):
+        pass
+    return out
+
+
+def cpu_baseline_full_gradients(args):
+    """CPU baseline leg, whole gradients: the FP64 oracle's gradient of the
+    benchmark recipe at 64^3 (one thread and every available core) and 128^3
+    (every available core), nt = 16, 64 Gaussians, rho_f = 10, k_f = 0.1,
+    rtol 1e-8, timed from the forward to Phi^T; the observation (threshold
+    of a perturbed-p oracle run) is made before the clock starts.  Needs no
+    GPU.  Prints one JSON object (the content of
+    profiles/cpu_oracle_gradients.json)."""
+    from oracle import spectral, tumor
+    from paper_1907_07774_amd import inputs
+    model, ncpu, avail = host_cpu()
+    runs = []
+    for n, workers in ((64, None), (64, avail), (128, avail)):
+        spectral.set_fft_workers(workers)
+        pr = inputs.problem(n, 4, 0, nt=16, rho_f=10.0, k_f=0.1)
+        su = tumor.Setup(pr.m, pr.centres, pr.sigma, pr.rho_f, pr.k_f, pr.nt, rtol=1e-8)
+        d = inputs.threshold_mask(tumor.forward(su, inputs.perturbed_p(pr.p, 0)).c[-1])
+        print(f"cpu-full {n}^3 x{workers or 1}: observation ready", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        tr = tumor.forward(su, pr.p)
+        print(f"cpu-full {n}^3 x{workers or 1}: forward {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
+        J, lam_t = tumor.misfit(su, tr.c[-1], d)
+        g = tumor.vjp(su, tr, lam_t)
+        sec = time.perf_counter() - t0
+        runs.append({"n": n, "threads": workers or 1, "seconds": sec,
+                     "gradient_evals_per_s": 1.0 / sec,
+                     "pcg_its": int(sum(tr.its) + sum(g.its)), "J": J})
+        print(json.dumps(runs[-1]), file=sys.stderr, flush=True)
+    spectral.set_fft_workers(None)
+    return {"workload": "FP64 oracle gradient, nt=16, 64 Gaussians, rho_f=10, k_f=0.1, "
+                        "PCG rtol 1e-8 (numpy.fft on 1 thread, else scipy.fft workers)",
+            "host_cpu": {"model": model, "logical_cpus": ncpu, "available_cpus": avail},
+            "command": "python bench.py --cpu-full", "runs": runs}
 
 
 def main():
     args = parse()
+    if args.cpu_full:
+        print(json.dumps(cpu_baseline_full_gradients(args)), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "tumorgrad runs each problem on one GPU: --gpus must be 1 "
                                    "(independent problems shard across GPUs with no exchange)",
@@ -590,14 +691,22 @@ def main():
     from paper_1907_07774_amd import api, inputs
 
     pr = inputs.problem(args.n, args.g, args.seed, nt=args.nt, T=1.0)
-    # synthetic observation: threshold of a run with perturbed coefficients
-    obs_plan = api.Plan(pr.n, pr.nt, pr.centres, pr.sigma, rtol=args.rtol,
-                        ckpt_stride=args.ckpt, precision="fp32")
     dev = torch.device("cuda:0")
-    cpo = obs_plan.forward(inputs.perturbed_p(pr.p, args.seed), pr.rho_f, pr.k_f,
-                           torch.tensor(pr.m, dtype=torch.float32, device=dev))
-    c_obs = (cpo > 0.5).to(torch.float64)
-    del obs_plan, cpo
+    # synthetic observation: threshold of a run with perturbed coefficients,
+    # the FP64 oracle's own (stored with its gradient of this workload) when
+    # available, so the gradients below are compared with the oracle's
+    oracle = load_oracle_gradient(np, args, pr)
+    if oracle is not None:
+        c_obs = torch.tensor(oracle["d"], dtype=torch.float64, device=dev)
+        obs_src = f"FP64 oracle threshold (stored, oracle PCG rtol {oracle['rtol']:g})"
+    else:
+        obs_plan = api.Plan(pr.n, pr.nt, pr.centres, pr.sigma, rtol=args.rtol,
+                            ckpt_stride=args.ckpt, precision="fp32")
+        cpo = obs_plan.forward(inputs.perturbed_p(pr.p, args.seed), pr.rho_f, pr.k_f,
+                               torch.tensor(pr.m, dtype=torch.float32, device=dev))
+        c_obs = (cpo > 0.5).to(torch.float64)
+        obs_src = "GPU FP32-mixed threshold"
+        del obs_plan, cpo
     torch.cuda.empty_cache()
 
     if args.copy_probe_mib:
@@ -637,6 +746,12 @@ def main():
 
     r32 = run_precision(torch, api, inputs, pr, c_obs, "fp32", args, args.steps, args.warmup,
                         args.timer_kernel, keep_state=not args.no_fp64, kernel_rates=True)
+    # FP32-mixed stopping floors (library defaults unless set in the environment)
+    eps32 = 1.1920928955078125e-07
+    env_floor = os.environ.get("TUMORGRAD_FP32_RTOL_FLOOR")
+    fp32_rtol = max(args.rtol, float(env_floor or 50 * eps32))
+    fp32_fwd_rtol = max(args.rtol, float(os.environ.get("TUMORGRAD_FP32_FWD_RTOL_FLOOR")
+                                         or env_floor or 16 * eps32))
     r64 = None
     if not args.no_fp64:
         r64 = run_precision(torch, api, inputs, pr, c_obs, "fp64", args, args.fp64_steps,
@@ -678,10 +793,16 @@ def main():
         "config": {
             "workload": (f"tumor forward+adjoint gradient, {args.n}^3 periodic grid, nt={args.nt}, "
                          f"T=1, {args.g ** 3} Gaussians, rho_f={pr.rho_f:.3f}, k_f={pr.k_f:.4f} "
-                         f"(seed {args.seed}), PCG rtol {args.rtol:g}, checkpoint stride "
-                         f"{args.ckpt}, FP32 fields/FFTs with FP64 reductions"),
+                         f"(seed {args.seed}), PCG rtol {args.rtol:g} requested; FP32-mixed "
+                         f"forward and recompute solves stop at {fp32_fwd_rtol:.1e}, adjoint "
+                         f"solves at {fp32_rtol:.1e} (worst final relative residual "
+                         f"{r32['worst_rel_residual']:.1e}), checkpoint stride {args.ckpt}, "
+                         f"FP32 fields/FFTs with FP64 reductions"),
             "grid": args.n, "nt": args.nt, "n_p": args.g ** 3, "seed": args.seed,
-            "rho_f": pr.rho_f, "k_f": pr.k_f, "rtol": args.rtol, "ckpt_stride": args.ckpt,
+            "rho_f": pr.rho_f, "k_f": pr.k_f, "rtol": args.rtol,
+            "fp32_effective_rtol_forward": fp32_fwd_rtol,
+            "fp32_effective_rtol_adjoint": fp32_rtol, "ckpt_stride": args.ckpt,
+            "observation": obs_src,
         },
         "roofline": roof,
         "pcg": {k: r32[k] for k in ("pcg_its_forward", "solves_forward", "pcg_its_adjoint",
@@ -693,11 +814,15 @@ def main():
         "step_ms_median": r32["step_ms_median"], "step_ms_min": r32["step_ms_min"],
         "kernel_rates_fp32": r32["kernel_rates"],
     }
+    if oracle is not None:
+        out["fp32_mixed_vs_oracle_rel_err"] = rel_errors(np, r32, oracle)
     if r64 is not None:
         gp32, gp64 = r32["gp"], r64["gp"]
         out["fp64"] = {
             "value": r64["value"], "ms_per_step": r64["ms_per_step"],
-            "speedup_fp32_mixed_over_fp64": r32["value"] / r64["value"],
+            # FP32-mixed stops at its floors (fp32_effective_rtol_*), FP64 at rtol:
+            # the two gradients are not equally accurate at this ratio
+            "speedup_at_requested_rtol_unequal_accuracy": r32["value"] / r64["value"],
             "fp32_vs_fp64_rel_err": {
                 "J": abs(r32["J"] - r64["J"]) / abs(r64["J"]),
                 "g_p": float(np.linalg.norm(gp32 - gp64) / np.linalg.norm(gp64)),
@@ -706,9 +831,17 @@ def main():
             },
             "pcg_its_forward": r64["pcg_its_forward"], "pcg_its_adjoint": r64["pcg_its_adjoint"],
         }
+        if oracle is not None:
+            out["fp64"]["fp64_vs_oracle_rel_err"] = rel_errors(np, r64, oracle)
         if not args.no_equal_accuracy:
-            out["fp64"]["equal_accuracy"] = equal_accuracy(torch, np, api, inputs, pr, c_obs,
-                                                           args, r32)
+            ea = equal_accuracy(torch, np, api, inputs, pr, c_obs, args, r32, oracle)
+            out["fp64"]["equal_accuracy"] = ea
+            if "speedup" in ea:
+                # the FP32-mixed / FP64 comparison: FP64 loosened until its
+                # gradient is as accurate as the FP32-mixed one
+                out["fp64"]["speedup"] = ea["speedup"]
+                out["fp64"]["speedup_basis"] = ("equal g_p accuracy against "
+                                                + ea["reference"])
     if not args.no_fixed:
         # the same workload at fixed (rho_f, k_f) = (10, 0.1): PCG iteration
         # counts grow with k_f, so the seed's k_f alone is not the whole story
