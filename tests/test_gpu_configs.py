@@ -3,9 +3,10 @@
 64^3 (forward, 8 Gaussians): element by element against the live oracle.
 128^3 (gradient, 64 Gaussians): against oracle values stored by
 tests/golden/make_golden.py, plus central finite differences of the FP64
-GPU path.  256^3 (the benchmark workload): sampled outputs the oracle can
-compute point by point (reaction-only closed form), stored sampled oracle
-forward values when present, and properties that hold at any size
+GPU path.  256^3 (the benchmark workload): the stored FP64 oracle gradient
+and Gauss-Newton products of exactly that workload, sampled outputs the
+oracle can compute point by point (reaction-only closed form), stored
+sampled oracle forward values, and properties that hold at any size
 (checkpoint recompute bitwise, FP32-mixed vs FP64, Hessian symmetry).
 """
 import os
@@ -160,6 +161,70 @@ def test_config3_forward_vs_oracle_samples_256(bench_problem):
         torch.cuda.empty_cache()
 
 
+def config3_golden(name="config3_256_grad.npz"):
+    """Stored FP64 oracle results of the benchmark workload (seed 0, 256^3,
+    nt = 32, 64 Gaussians) with the oracle's own observation."""
+    g = load_golden(name)
+    pr = inputs.problem(int(g["n"]), 4, int(g["seed"]), nt=int(g["nt"]))
+    assert abs(pr.rho_f - float(g["rho_f"])) < 1e-12 and abs(pr.k_f - float(g["k_f"])) < 1e-12
+    return g, pr
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_config3_gradient_vs_oracle_256(prec):
+    """The benchmark workload at full size against the FP64 oracle's
+    gradient (tests/golden/make_golden.py config3grad, oracle PCG rtol
+    1e-10, its own thresholded observation).  FP64 at the same rtol is held
+    to 100 rtol = 1e-8 (reading C12: two solvers stopped at rtol differ by
+    up to that); FP32-mixed to 1e-4 relative (vector L2 for c(T) samples
+    and g_p)."""
+    print(f"case config3 gradient vs oracle {prec}", flush=True)
+    g, pr = config3_golden()
+    n = pr.n
+    d = np.unpackbits(g["d_bits"])[:n ** 3].astype(np.float64).reshape(n, n, n)
+    rtol = float(g["rtol"])
+    plan = api.Plan(n, pr.nt, pr.centres, pr.sigma, rtol=rtol, precision=prec, ckpt_stride=4)
+    cT = plan.forward(pr.p, pr.rho_f, pr.k_f, pr.m).cpu().numpy().ravel()
+    J, gp, gr, gk = plan.adjoint_misfit(d)
+    assert plan.stats().status_bits == 0
+    tol = 100 * rtol if prec == "fp64" else 1e-4
+    errs = {"cT": rel(cT[g["idx"]], g["cT"]),
+            "J": abs(float(J) - float(g["J"])) / abs(float(g["J"])),
+            "g_p": rel(gp.cpu().numpy(), g["g_p"]),
+            "g_rho": abs(float(gr) - float(g["g_rho"])) / abs(float(g["g_rho"])),
+            "g_k": abs(float(gk) - float(g["g_k"])) / abs(float(g["g_k"]))}
+    print(f"  {prec} errors vs oracle: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()),
+          flush=True)
+    for k, v in errs.items():
+        assert v < tol, (k, v)
+    del plan
+    torch.cuda.empty_cache()
+
+
+def test_config5_hessvec_vs_oracle_256():
+    """Gauss-Newton products at 256^3 about the benchmark trajectory
+    against the FP64 oracle's (first two of the eight benchmark
+    directions; oracle PCG rtol 1e-10): FP64 at the same rtol to 1e-8,
+    FP32-mixed (all eight directions batched in one call, as in the
+    benchmark) to 1e-4 relative L2 on the two with oracle values."""
+    print("case config5 hessvec vs oracle", flush=True)
+    h, pr = config3_golden("config5_256_hvp.npz")
+    V = inputs.hvp_directions(8, pr.p.size, int(h["dir_seed"]))
+    assert np.array_equal(V[:2], h["V"])
+    rtol = float(h["rtol"])
+    for prec, nd, tol in (("fp64", 2, 100 * rtol), ("fp32", 8, 1e-4)):
+        plan = api.Plan(pr.n, pr.nt, pr.centres, pr.sigma, rtol=rtol, precision=prec,
+                        ckpt_stride=4, max_hvp_dirs=nd)
+        plan.forward(pr.p, pr.rho_f, pr.k_f, pr.m)
+        HV = plan.hessvec(V[:nd]).cpu().numpy()
+        assert plan.stats().status_bits == 0
+        errs = [rel(HV[i], h["HV"][i]) for i in range(2)]
+        print(f"  {prec} GN product errors vs oracle: {errs[0]:.2e}, {errs[1]:.2e}", flush=True)
+        assert max(errs) < tol, (prec, errs)
+        del plan
+        torch.cuda.empty_cache()
+
+
 @pytest.fixture(scope="module")
 def grads_256(bench_problem):
     """FP64 and FP32-mixed gradients of the benchmark workload, plus the
@@ -185,6 +250,29 @@ def test_config3_checkpoint_recompute_bitwise_256(grads_256):
     a, b = grads_256["fp32"], grads_256["fp32_nockpt"]
     assert a[0] == b[0] and a[2] == b[2] and a[3] == b[3]
     assert np.array_equal(a[1], b[1])
+
+
+def test_config3_repeated_calls_bitwise_256(bench_problem):
+    """Two identical gradient evaluations on one plan give the same bits
+    (the benchmark repeats exactly this).  Every forward solve after the
+    first starts from the previous step's increment, which the forward
+    keeps in the workspace from call to call: the increment entering each
+    call is rebuilt from scratch (step 0 starts from a alone), so nothing of
+    the previous call leaks into the next."""
+    print("case config3 repeated calls bitwise", flush=True)
+    pr = bench_problem
+    d = (inputs.random_field(256, 9) > 0.2).astype(np.float32)
+    plan = api.Plan(256, 32, pr.centres, pr.sigma, rtol=1e-8, precision="fp32", ckpt_stride=4)
+    runs = []
+    for _ in range(2):
+        cT = plan.forward(pr.p, pr.rho_f, pr.k_f, pr.m).cpu().numpy()
+        J, gp, gr, gk = plan.adjoint_misfit(d)
+        runs.append((cT, float(J), gp.cpu().numpy(), float(gr), float(gk)))
+    a, b = runs
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[2], b[2])
+    assert a[1] == b[1] and a[3] == b[3] and a[4] == b[4]
+    del plan
+    torch.cuda.empty_cache()
 
 
 def test_config3_fp32_mixed_vs_fp64_256(grads_256):
