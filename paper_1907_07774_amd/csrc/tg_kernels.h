@@ -78,6 +78,32 @@ __device__ __forceinline__ double* part_at(double* part, int b, int s) {
   return part + ((size_t)b * NSLOT + s) * MAXBLK;
 }
 
+// PCG step length of problem b (called by every thread of one workgroup of
+// NT threads): <p, A p> = sum w |p|^2 + tau k_f n^3 sum_x m |grad p|^2 from
+// the partial sums of the x inverse pass (slot 0, nblk0 of them) and of the
+// z matvec (slot 1, nblk1), summed in a fixed order (scale = tau n^3), then
+// alpha = <r, M r> / <p, A p>, or a breakdown.  red: NSLOT * NT/64 doubles.
+template <int NT>
+__device__ void pcg_step_length(ProbScalars& S, double* part, int b, int nblk0, int nblk1,
+                                double scale, double* red) {
+  double acc[NSLOT] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < nblk0; i += NT) acc[0] += part_at(part, b, 0)[i];
+  for (int i = threadIdx.x; i < nblk1; i += NT) acc[1] += part_at(part, b, 1)[i];
+  block_sums<NT>(acc, 2, red);
+  if (threadIdx.x != 0) return;
+  const double pap = acc[0] + scale * S.kf * acc[1];
+  S.pq = pap;
+  if (!(pap > 0.0) || !isfinite(pap)) {
+    S.status |= isfinite(pap) ? STAT_BREAKDOWN : STAT_NONFINITE;
+    S.done = 1;
+    S.alpha = 0.0;
+    const double rel = S.rhs2 > 0 ? sqrt(S.rr / S.rhs2) : 0.0;
+    S.worst = fmax(S.worst, rel);
+  } else {
+    S.alpha = S.rho / pap;
+  }
+}
+
 // ------------------------------------------------------ strided passes
 // Pass along x (AX = 0) or y (AX = 1) of a packed spectrum.  Column index
 // gc enumerates the n * n/2 pencils: for x, gc = ky * n/2 + kz'; for y,
@@ -201,11 +227,19 @@ k_y_inv_grad(cx<T>* __restrict__ U1, cx<T>* __restrict__ U2, cx<T>* __restrict__
 
 // ---- y pass, forward: W1 = FFT_y(H1) (in place), W23 = i wy FFT_y(H2) +
 // FFT_y(H3) (into H2).  FP32 loads all three inputs before any FFT.
+// fin0 > 0 (last launch of a PCG iteration's matvec): workgroup 0 of each
+// problem also forms the PCG step length (pcg_step_length with fin0, fin1
+// partials and scale fsc); the x forward pass that follows reads it.
 template <typename T, int N, int C, int OCC>
 __global__ void TG_BOUNDS((SP<T, N, C, 1>::NT), OCC)
 k_y_fwd_div(cx<T>* __restrict__ H1, cx<T>* __restrict__ H2, const cx<T>* __restrict__ H3,
-            const ProbScalars* __restrict__ sc, int pred, int blk0) {
+            ProbScalars* __restrict__ sc, int pred, int blk0, double* __restrict__ part,
+            int fin0, int fin1, double fsc) {
   SP_SETUP_EXIT(1, blk0, pred && sc[blockIdx.y].done)
+  if (fin0 > 0 && blockIdx.x == 0) {
+    __shared__ double red[NSLOT * ((S::NT + 63) / 64)];
+    pcg_step_length<S::NT>(sc[b], part, b, fin0, fin1, fsc, red);
+  }
   constexpr bool PRE = sizeof(T) == 4;
   cx<T> v[E], a[E], c[E];
 #pragma unroll
@@ -1003,7 +1037,7 @@ __global__ void __launch_bounds__(256) k_zero(T* __restrict__ dst, long long n) 
 // ---------------------------------------------------------- finalizers
 enum FinMode : int {
   FIN_INIT = 0,   // slots: |rhs|^2, <r,Mr>, |r|^2
-  FIN_PAP = 1,    // slots: |p|^2 (nblk), sum m |grad p|^2 (nblk2) -> <p, A p>, alpha
+  FIN_PAP = 1,    // (the step length: pcg_step_length, inside the y forward pass)
   FIN_RZ = 2,     // slots: <r,Mr>, |r|^2
   FIN_GRHO = 3,   // slot: g_rho increment
   FIN_GK = 4,     // slot: spectral <Am mu, s>
@@ -1016,13 +1050,13 @@ enum FinMode : int {
 template <int MODE, int NT = 256>
 __global__ void __launch_bounds__(NT)
 k_finalize(ProbScalars* __restrict__ sc, const double* __restrict__ part, int nblk,
-           double scale_, double rtol, int maxit, int nblk2 = 0) {
+           double scale_, double rtol, int maxit) {
   constexpr int NW = NT / 64;
   __shared__ double red[NSLOT * NW];
   const int b = blockIdx.x;
   ProbScalars& S = sc[b];
-  if ((MODE == FIN_PAP || MODE == FIN_RZ) && S.done) return;
-  constexpr int ns = MODE == FIN_INIT ? 3 : (MODE == FIN_RZ || MODE == FIN_PAP) ? 2 : 1;
+  if (MODE == FIN_RZ && S.done) return;
+  constexpr int ns = MODE == FIN_INIT ? 3 : MODE == FIN_RZ ? 2 : 1;
   double acc[NSLOT] = {0.0, 0.0, 0.0, 0.0};
   if constexpr (MODE == FIN_MMAX) {
     double mx = 0.0;
@@ -1038,10 +1072,8 @@ k_finalize(ProbScalars* __restrict__ sc, const double* __restrict__ part, int nb
     }
     return;
   }
-  for (int s = 0; s < ns; ++s) {
-    const int nb = (MODE == FIN_PAP && s == 1) ? nblk2 : nblk;
-    for (int i = threadIdx.x; i < nb; i += NT) acc[s] += part_at((double*)part, b, s)[i];
-  }
+  for (int s = 0; s < ns; ++s)
+    for (int i = threadIdx.x; i < nblk; i += NT) acc[s] += part_at((double*)part, b, s)[i];
   block_sums<NT>(acc, ns, red);
   if (threadIdx.x != 0) return;
   if constexpr (MODE == FIN_INIT) {
@@ -1062,20 +1094,6 @@ k_finalize(ProbScalars* __restrict__ sc, const double* __restrict__ part, int nb
     if (S.done) {
       const double rel = S.rhs2 > 0 ? sqrt(S.rr / S.rhs2) : 0.0;
       S.worst = fmax(S.worst, rel);
-    }
-  } else if constexpr (MODE == FIN_PAP) {
-    // spectral sums: <p, A p> = sum w |p|^2 + tau k_f n^3 sum_x m |grad p|^2
-    // (scale_ = tau n^3)
-    const double pap = acc[0] + scale_ * S.kf * acc[1];
-    S.pq = pap;
-    if (!(pap > 0.0) || !isfinite(pap)) {
-      S.status |= isfinite(pap) ? STAT_BREAKDOWN : STAT_NONFINITE;
-      S.done = 1;
-      S.alpha = 0.0;
-      const double rel = S.rhs2 > 0 ? sqrt(S.rr / S.rhs2) : 0.0;
-      S.worst = fmax(S.worst, rel);
-    } else {
-      S.alpha = S.rho / pap;
     }
   } else if constexpr (MODE == FIN_RZ) {
     const double rho_new = acc[0];

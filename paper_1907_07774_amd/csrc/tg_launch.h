@@ -51,8 +51,10 @@ struct Sched {
   // y-pass and z-pass launches over slab k of nslab (x-plane ranges)
   void (*y_inv_grad)(cx<T>* U1, cx<T>* U2, cx<T>* V3, const ProbScalars* sc, int pred, int nb,
                      int k, int nslab, hipStream_t st) = nullptr;
-  void (*y_fwd_div)(cx<T>* H1, cx<T>* H2, const cx<T>* H3, const ProbScalars* sc, int pred, int nb,
-                    int k, int nslab, hipStream_t st) = nullptr;
+  // fin0 > 0: the launch also forms the PCG step length (k_y_fwd_div)
+  void (*y_fwd_div)(cx<T>* H1, cx<T>* H2, const cx<T>* H3, ProbScalars* sc, int pred, int nb,
+                    int k, int nslab, double* part, int fin0, int fin1, double fsc,
+                    hipStream_t st) = nullptr;
   void (*x_fwd_div)(int mode, const cx<T>* W1, const cx<T>* W23, cx<T>* X, cx<T>* Q,
                     const cx<T>* Sv, const ProbScalars* sc, double* part, double tau, int pred,
                     int want_gk, int nb, hipStream_t st) = nullptr;
@@ -89,10 +91,12 @@ struct SLaunch {
     const int nbk = SY::NBLK / nslab;
     klaunch(k_y_inv_grad<T, N, C, OCC>, dim3(nbk, nb), dim3(SY::NT), st, U1, U2, V3, sc, pred, k * nbk);
   }
-  static void y_fwd_div(cx<T>* H1, cx<T>* H2, const cx<T>* H3, const ProbScalars* sc, int pred,
-                        int nb, int k, int nslab, hipStream_t st) {
+  static void y_fwd_div(cx<T>* H1, cx<T>* H2, const cx<T>* H3, ProbScalars* sc, int pred,
+                        int nb, int k, int nslab, double* part, int fin0, int fin1, double fsc,
+                        hipStream_t st) {
     const int nbk = SY::NBLK / nslab;
-    klaunch(k_y_fwd_div<T, N, C, OCC>, dim3(nbk, nb), dim3(SY::NT), st, H1, H2, H3, sc, pred, k * nbk);
+    klaunch(k_y_fwd_div<T, N, C, OCC>, dim3(nbk, nb), dim3(SY::NT), st, H1, H2, H3, sc, pred,
+            k * nbk, part, fin0, fin1, fsc);
   }
   static void x_fwd_div(int mode, const cx<T>* W1, const cx<T>* W23, cx<T>* X, cx<T>* Q,
                         const cx<T>* Sv, const ProbScalars* sc, double* part, double tau, int pred,

@@ -416,7 +416,9 @@ class Solver final : public ISolver {
   // three passes run slab by slab over nslab x-plane ranges so each slab's
   // intermediates can stay in the last-level cache between passes.
   // The z pass also leaves the partial sums of m |grad u|^2 (slot 1).
-  void matvec_mid(const Ctx& c, cx<T>* U1, cx<T>* U2, cx<T>* V3, int pred) {
+  // step: inside a PCG iteration, the last y forward launch also forms the
+  // step length from those and the x inverse pass's |p|^2 partials.
+  void matvec_mid(const Ctx& c, cx<T>* U1, cx<T>* U2, cx<T>* V3, int pred, bool step = false) {
     const int work = pred ? 0 : c.nb;
     const int ns = nslab_;
     for (int k = 0; k < ns; ++k) {
@@ -426,8 +428,10 @@ class Solver final : public ISolver {
       timed(KT_Z_MATVEC, k == 0 ? work : 0, [&] {
         sch_.z_matvec(U1, U2, V3, c.m, c.m_bs, c.sc, c.part, pred, 1, c.nb, k, ns, st_);
       });
+      const bool fin = step && k == ns - 1;
       timed(KT_Y_FWD_DIV, k == 0 ? work : 0, [&] {
-        sch_.y_fwd_div(U1, U2, V3, c.sc, pred, c.nb, k, ns, st_);
+        sch_.y_fwd_div(U1, U2, V3, c.sc, pred, c.nb, k, ns, c.part, fin ? sch_.xi_nblk : 0,
+                       sch_.zm_nblk, tau_ * (double)REAL, st_);
       });
     }
   }
@@ -508,10 +512,7 @@ class Solver final : public ISolver {
     timed(KT_X_INV_GRAD, 0, [&] {
       sch_.x_inv_grad(1, c.P, c.R, c.T1, c.T2, c.sc, c.part, tau_, 1, c.nb, st_);
     });
-    matvec_mid(c, c.T1, c.T2, c.T3, 1);
-    k_finalize<FIN_PAP, 1024><<<c.nb, 1024, 0, st_>>>(c.sc, c.part, sch_.xi_nblk,
-                                                     tau_ * (double)REAL, rtol(), maxit(),
-                                                     sch_.zm_nblk);
+    matvec_mid(c, c.T1, c.T2, c.T3, 1, /*step=*/true);
     timed(KT_X_FWD_DIV, 0, [&] {
       sch_.x_fwd_div(XM_PCG, c.T1, c.T2, c.X, c.R, c.P, c.sc, c.part, tau_, 1, 0, c.nb, st_);
     });
