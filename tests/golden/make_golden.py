@@ -5,6 +5,7 @@ generators).
     python tests/golden/make_golden.py config2      # 128^3 gradient
     python tests/golden/make_golden.py config3fwd   # 256^3 forward, sampled
     python tests/golden/make_golden.py config3grad  # 256^3 gradient + 2 GN products
+    python tests/golden/make_golden.py config5hvp   # the 2 GN products alone
 
 Outputs are small .npz files next to this script: scalars, the full
 gradient vector and c(T) at a seeded sample of grid points.  The 256^3
@@ -119,6 +120,28 @@ def config3grad(rtol=1e-10):
                         rho_f=pr.rho_f, k_f=pr.k_f, rtol=rtol, dir_seed=0, V=V,
                         HV=np.array(HV))
     _log(t0, "config3grad done")
+
+
+def config5hvp(rtol=1e-10):
+    """The Gauss-Newton products of config3grad alone (its own forward
+    trajectory of the benchmark problem): config5_256_hvp.npz."""
+    from oracle import spectral
+    spectral.set_fft_workers(int(os.environ.get("TG_ORACLE_FFT_WORKERS", "6")))
+    n, nt, seed = 256, 32, 0
+    pr = inputs.problem(n, 4, seed, nt=nt)
+    su = tumor.Setup(pr.m, pr.centres, pr.sigma, pr.rho_f, pr.k_f, nt, rtol=rtol)
+    t0 = time.time()
+    tr = tumor.forward(su, pr.p)
+    _log(t0, f"forward: {sum(tr.its)} its")
+    V = inputs.hvp_directions(8, pr.p.size, 0)[:2]
+    HV = []
+    for i, v in enumerate(V):
+        HV.append(tumor.gn_hvp(su, tr, v))
+        _log(t0, f"GN product {i}: |Hv| = {np.linalg.norm(HV[-1]):.6e}")
+    np.savez_compressed(os.path.join(HERE, "config5_256_hvp.npz"), n=n, nt=nt, seed=seed,
+                        rho_f=pr.rho_f, k_f=pr.k_f, rtol=rtol, dir_seed=0, V=V,
+                        HV=np.array(HV))
+    _log(t0, "config5hvp done")
 
 
 if __name__ == "__main__":
