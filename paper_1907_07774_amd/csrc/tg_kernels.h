@@ -987,42 +987,79 @@ __global__ void __launch_bounds__((ZP<T, N, RW>::NT)) k_z_step(ZArgs a) {
 // gradient rows of mu (M1, M2, M3) and of s = a + b (S1, S2, S3) as the
 // matvec's y pass leaves them (row 3 still needs i wz before the z
 // transform).  One pass over six spectral rows and the real output row.
-template <typename T, int N, int RW>
-__global__ void __launch_bounds__((ZP<T, N, RW>::NT)) k_z_qgrad(
+// Spectral rows are read in pair layout (16-byte accesses in FP32); in FP32
+// the next pair of rows (and, for the last, the output row) is loaded
+// before the current pair is transformed, so loads overlap the transforms.
+template <typename T, int N, int RW, int OCC, bool PF>
+__global__ void TG_BOUNDS((ZP<T, N, RW>::NT), OCC) k_z_qgrad(
     const cx<T>* __restrict__ M1, const cx<T>* __restrict__ M2, const cx<T>* __restrict__ M3,
     const cx<T>* __restrict__ S1, const cx<T>* __restrict__ S2, const cx<T>* __restrict__ S3,
     T* __restrict__ Qk, const ProbScalars* __restrict__ sc, double tau) {
   ZP_SETUP
   const cx<T>* Ms[3] = {M1 + sbase, M2 + sbase, M3 + sbase};
   const cx<T>* Ss[3] = {S1 + sbase, S2 + sbase, S3 + sbase};
-  cx<T> acc[E], u[E], w[E];
+  cx<T>* q = reinterpret_cast<cx<T>*>(Qk + b * Z::REAL + grow * N);
+  auto load_pairs = [&](const cx<T>* row_, cx<T>(&u)[E]) {
+    const cx2<T>* r2 = reinterpret_cast<const cx2<T>*>(row_);
+#pragma unroll
+    for (int e = 0; e < E / 2; ++e) {
+      const cx2<T> w = r2[t + TT * e];
+      u[2 * e] = w.a;
+      u[2 * e + 1] = w.b;
+    }
+  };
+  cx<T> acc[E], u[E], w[E], un[PF ? E : 1], wn[PF ? E : 1];
 #pragma unroll
   for (int e = 0; e < E; ++e) acc[e] = mk(T(0), T(0));
+  load_pairs(Ms[0], u);
+  load_pairs(Ss[0], w);
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
+    // keep the compiler from hoisting later rows' loads above the previous
+    // transforms (it would hold all six rows in registers at once)
+    asm volatile("" ::: "memory");
+    if constexpr (PF) {
+      if (j < 2) {
+        load_pairs(Ms[j + 1], un);
+        load_pairs(Ss[j + 1], wn);
+      } else {
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      u[e] = Ms[j][t + TT * e];
-      w[e] = Ss[j][t + TT * e];
+        for (int e = 0; e < E; ++e) un[e] = q[t + TT * e];
+      }
+    } else if (j > 0) {
+      load_pairs(Ms[j], u);
+      load_pairs(Ss[j], w);
     }
     if (j == 2) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const T kz = (T)(t + TT * e);  // slot 0 (kz = 0 and n/2) has no z derivative
-        u[e] = mul_i(u[e], kz);
-        w[e] = mul_i(w[e], kz);
+      for (int i = 0; i < E; ++i) {
+        // spectral position of register i; slot 0 (kz = 0 and n/2) has no z derivative
+        const T kz = (T)(2 * (t + TT * (i / 2)) + (i & 1));
+        u[i] = mul_i(u[i], kz);
+        w[i] = mul_i(w[i], kz);
       }
     }
-    c2r_row<T, N>(u, lds, t, row);
-    c2r_row<T, N>(w, lds, t, row);
+    c2r_pairs<T, N>(u, lds, t, row);
+    c2r_pairs<T, N>(w, lds, t, row);
 #pragma unroll
-    for (int e = 0; e < E; ++e) acc[e] = mk(acc[e].x + u[e].x * w[e].x, acc[e].y + u[e].y * w[e].y);
+    for (int e = 0; e < E; ++e) {
+      acc[e] = mk(acc[e].x + u[e].x * w[e].x, acc[e].y + u[e].y * w[e].y);
+      asm volatile("" : "+v"(acc[e].x), "+v"(acc[e].y));  // form the sum here
+    }
+    if constexpr (PF) {
+      if (j < 2) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          u[e] = un[e];
+          w[e] = wn[e];
+        }
+      }
+    }
   }
   const T cs = (T)(-tau * sc[b].kf);
-  cx<T>* q = reinterpret_cast<cx<T>*>(Qk + b * Z::REAL + grow * N);
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    const cx<T> o = q[t + TT * e];
+    const cx<T> o = PF ? un[PF ? e : 0] : q[t + TT * e];
     q[t + TT * e] = mk(o.x + cs * acc[e].x, o.y + cs * acc[e].y);
   }
 }

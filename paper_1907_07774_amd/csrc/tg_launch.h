@@ -192,7 +192,11 @@ struct ZLaunch {
   static void z_qgrad(const cx<T>* M1, const cx<T>* M2, const cx<T>* M3, const cx<T>* S1,
                       const cx<T>* S2, const cx<T>* S3, T* Qk, const ProbScalars* sc,
                       double tau, int nb, hipStream_t st) {
-    k_z_qgrad<T, N, RW><<<dim3(Z::NBLK, nb), Z::NT, 0, st>>>(M1, M2, M3, S1, S2, S3, Qk, sc, tau);
+    // FP32: two waves per SIMD with the next rows prefetched (254 VGPRs at
+    // 256^3, no spills); FP64 rows are twice the registers: one wave, no
+    // prefetch (a floor of two spills)
+    constexpr bool F32 = sizeof(T) == 4;
+    k_z_qgrad<T, N, RW, F32 ? 2 : 1, F32><<<dim3(Z::NBLK, nb), Z::NT, 0, st>>>(M1, M2, M3, S1, S2, S3, Qk, sc, tau);
   }
   static void fill(Sched<T, N>& s) {
     s.RW = RW;
