@@ -1345,9 +1345,10 @@ __global__ void k_basis_factors(const double* __restrict__ centres, long long c_
 // rows of k_basis_factors), so both Phi p and Phi^T lam are contractions
 // over the Gaussians i and the z axis of a grid row r = (x, y) with the z
 // factors: [n^2 x n_p] by [n_p x n] and [n^2 x n] by [n x n_p] products.
-// They run as register-tiled products in FP64 (workgroups of 256 threads,
-// 64 rows per workgroup, operands staged through LDS), reading and writing
-// each field once.
+// They run as register-tiled products in FP64 (k_phi and k_phit: workgroups
+// of 256 threads, 64 rows per workgroup, operands staged through LDS; from
+// n = 128 on Phi p runs as k_phi_w, with the row factors in scalar
+// registers), reading and writing each field once.
 
 // ---- c0 = w Phi p (w: the CSF mask of Sec. 2.1, or none): for each row
 // r = (x, y), c0[r][z] = w sum_i a_i(r) gz_i[z] with a_i(r) = p_i gx_i[x]
@@ -1443,6 +1444,87 @@ __global__ void __launch_bounds__(256) k_phi(const double* __restrict__ p, long 
       double v = acc[q][a];
       if (mask) v *= (double)mask[b * mask_bs + o + K::TZ * a];
       out[b * out_bs + o + K::TZ * a] = (T)v;
+    }
+  }
+}
+
+// ---- c0 = w Phi p for n >= 128, without LDS: lane l holds z = l + 64 k
+// (k < n/64) of RW rows (x, y0 .. y0 + RW - 1) that are the same for the
+// whole wave, so per Gaussian the row factors a_i(r) = (p_i gx_i[x]) gy_i[y]
+// are wave-uniform values (p_i, gx_i[x] and gy_i[y] come through the scalar
+// cache) and only gz_i[z] is per lane.  Per Gaussian a lane does
+// RW n/64 = 32 multiply-adds and RW + 1 products; stores are 64 consecutive
+// z per wave.  The sums run over i in the same order and with the same
+// rounding as k_phi.
+template <int N>
+struct PhiW {
+  static constexpr int ZT = N / 64;                // z values per lane
+  static constexpr int RW = 32 / ZT;               // rows per wave
+  static constexpr int WV = N >= 256 ? 4 : 2;      // waves per workgroup
+  static constexpr int NBLK = N * N / (RW * WV);   // workgroups per problem
+  static_assert(N >= 128 && N % RW == 0, "PhiW needs n >= 128");
+};
+
+template <typename T, int N>
+__global__ void TG_BOUNDS(64 * PhiW<N>::WV, 2)
+k_phi_w(const double* __restrict__ p, long long p_bs, const double* __restrict__ g,
+        long long g_bs, const T* __restrict__ mask, long long mask_bs, T* __restrict__ out,
+        long long out_bs, int n_p) {
+  using K = PhiW<N>;
+  constexpr int ZT = K::ZT, RW = K::RW;
+  const int b = blockIdx.y;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r0 = (blockIdx.x * K::WV + wv) * RW;   // first row of this wave
+  const int x = r0 / N, y0 = r0 % N;
+  const double* gb = g + b * g_bs;
+  const double* pb = p + b * p_bs;
+  double acc[RW][ZT];
+#pragma unroll
+  for (int j = 0; j < RW; ++j)
+#pragma unroll
+    for (int k = 0; k < ZT; ++k) acc[j][k] = 0.0;
+  // Two operand sets alternate: the operands of Gaussian i + 1 (clamped to
+  // the last one) are fetched while Gaussian i is multiplied.  Scalar loads
+  // can only be waited for all together, so each fetch is issued after the
+  // first use of the other set (the scheduling barriers keep that order):
+  // the wait before that use then covers only the loads of one Gaussian
+  // earlier.  (Loaded as vector loads instead, the uniform row factors cost
+  // 4 KB of L1 return traffic per wave and Gaussian: twice as slow.)
+  double zs[2][ZT], gys[2][RW], ps[2], gxs[2];
+  auto fetch = [&](int st, int i) {
+#pragma unroll
+    for (int k = 0; k < ZT; ++k) zs[st][k] = gb[((size_t)i * 3 + 2) * N + lane + 64 * k];
+#pragma unroll
+    for (int j = 0; j < RW; ++j) gys[st][j] = gb[((size_t)i * 3 + 1) * N + y0 + j];
+    ps[st] = pb[i];
+    gxs[st] = gb[((size_t)i * 3) * N + x];
+  };
+  auto gauss = [&](int st, int i) {
+    const double w = ps[st] * gxs[st];
+    __builtin_amdgcn_sched_barrier(0);
+    fetch(st ^ 1, min(i + 1, n_p - 1));
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < RW; ++j) {
+      const double a = w * gys[st][j];
+#pragma unroll
+      for (int k = 0; k < ZT; ++k) acc[j][k] = fma(a, zs[st][k], acc[j][k]);
+    }
+  };
+  if (n_p > 0) fetch(0, 0);
+  for (int i = 0; i < n_p; i += 2) {
+    gauss(0, i);
+    if (i + 1 < n_p) gauss(1, i + 1);
+  }
+#pragma unroll
+  for (int j = 0; j < RW; ++j) {
+    const long long o = (long long)(r0 + j) * N + lane;
+#pragma unroll
+    for (int k = 0; k < ZT; ++k) {
+      double v = acc[j][k];
+      if (mask) v *= (double)mask[b * mask_bs + o + 64 * k];
+      out[b * out_bs + o + 64 * k] = (T)v;
     }
   }
 }

@@ -159,8 +159,7 @@ class Solver final : public ISolver {
     k_basis_factors<<<dim3((nf + 255) / 256, d_.batch), 256, 0, st_>>>(
         w_.centres, (long long)d_.n_p * 3, w_.gfac, N, d_.n_p, d_.sigma);
     TG_LAUNCH_CHECK();
-    k_phi<T, N><<<dim3(PhiK<N>::NBX * PhiK<N>::NBZ, d_.batch), 256, 0, st_>>>(
-        p, d_.n_p, w_.gfac, (long long)d_.n_p * 3 * N, mask_, REAL, ck(0), REAL, d_.n_p);
+    launch_phi(p, d_.n_p, w_.gfac, (long long)d_.n_p * 3 * N, mask_, REAL, ck(0), REAL, d_.batch);
     TG_LAUNCH_CHECK();
     TG_CHECK(fwd_steps(c, 0, d_.nt, /*initial=*/true));
     live_seg_ = d_.nseg - 1;
@@ -227,8 +226,7 @@ class Solver final : public ISolver {
     k_copy_dir_scalars<<<(ndir + 63) / 64, 64, 0, st_>>>(w_.sc, dc.sc, ndir);
     TG_LAUNCH_CHECK();
     // dc0 = Phi v for each direction
-    k_phi<T, N><<<dim3(PhiK<N>::NBX * PhiK<N>::NBZ, ndir), 256, 0, st_>>>(V, d_.n_p, w_.gfac, 0, mask_, 0,
-                                                          lam(0), REAL, d_.n_p);
+    launch_phi(V, d_.n_p, w_.gfac, 0, mask_, 0, lam(0), REAL, ndir);
     TG_LAUNCH_CHECK();
     // tangent sweep, forward in time
     for (int j = 0; j < d_.nseg; ++j) {
@@ -396,6 +394,17 @@ class Solver final : public ISolver {
     a.Xs = c.T1;
     a.Y2 = c.S;
     return a;
+  }
+
+  // c0 = w Phi p for nb problems (p, g, mask, out with their batch strides)
+  void launch_phi(const double* p, long long p_bs, const double* g, long long g_bs,
+                  const T* mask, long long mask_bs, T* out, long long out_bs, int nb) {
+    if constexpr (N >= 128)
+      k_phi_w<T, N><<<dim3(PhiW<N>::NBLK, nb), 64 * PhiW<N>::WV, 0, st_>>>(
+          p, p_bs, g, g_bs, mask, mask_bs, out, out_bs, d_.n_p);
+    else
+      k_phi<T, N><<<dim3(PhiK<N>::NBX * PhiK<N>::NBZ, nb), 256, 0, st_>>>(
+          p, p_bs, g, g_bs, mask, mask_bs, out, out_bs, d_.n_p);
   }
 
   template <int MODE>
