@@ -122,9 +122,10 @@ def config3grad(rtol=1e-10):
     _log(t0, "config3grad done")
 
 
-def config5hvp(rtol=1e-10):
+def config5hvp(rtol=1e-10, dirs=(0, 1), name="config5_256_hvp.npz"):
     """The Gauss-Newton products of config3grad alone (its own forward
-    trajectory of the benchmark problem): config5_256_hvp.npz."""
+    trajectory of the benchmark problem) along benchmark directions `dirs`
+    (indices into the eight of inputs.hvp_directions, seed 0): `name`."""
     from oracle import spectral
     spectral.set_fft_workers(int(os.environ.get("TG_ORACLE_FFT_WORKERS", "6")))
     n, nt, seed = 256, 32, 0
@@ -133,15 +134,21 @@ def config5hvp(rtol=1e-10):
     t0 = time.time()
     tr = tumor.forward(su, pr.p)
     _log(t0, f"forward: {sum(tr.its)} its")
-    V = inputs.hvp_directions(8, pr.p.size, 0)[:2]
+    V = inputs.hvp_directions(8, pr.p.size, 0)[list(dirs)]
     HV = []
-    for i, v in enumerate(V):
+    for i, v in zip(dirs, V):
         HV.append(tumor.gn_hvp(su, tr, v))
         _log(t0, f"GN product {i}: |Hv| = {np.linalg.norm(HV[-1]):.6e}")
-    np.savez_compressed(os.path.join(HERE, "config5_256_hvp.npz"), n=n, nt=nt, seed=seed,
-                        rho_f=pr.rho_f, k_f=pr.k_f, rtol=rtol, dir_seed=0, V=V,
-                        HV=np.array(HV))
+    np.savez_compressed(os.path.join(HERE, name), n=n, nt=nt, seed=seed,
+                        rho_f=pr.rho_f, k_f=pr.k_f, rtol=rtol, dir_seed=0,
+                        dirs=np.array(dirs), V=V, HV=np.array(HV))
     _log(t0, "config5hvp done")
+
+
+def config5hvp_d1(rtol=1e-10):
+    """Direction 1 alone (for a second process next to config5hvp):
+    config5_256_hvp_d1.npz."""
+    config5hvp(rtol, dirs=(1,), name="config5_256_hvp_d1.npz")
 
 
 if __name__ == "__main__":
