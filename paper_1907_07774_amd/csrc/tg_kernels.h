@@ -109,11 +109,11 @@ __device__ void pcg_step_length(ProbScalars& S, double* part, int b, int nblk0, 
 // gc enumerates the n * n/2 pencils: for x, gc = ky * n/2 + kz'; for y,
 // gc = x * n/2 + kz'.  A workgroup takes C consecutive pencils; thread
 // (col, t) holds positions t + TT e of pencil col.
-template <typename T, int N, int C, int AX>
+template <typename T, int N, int C, int AX, int E_ = FftE<N>::value>
 struct SP {
   static constexpr int NH = N / 2;
   static constexpr int L = N;
-  static constexpr int E = FftE<N>::value;
+  static constexpr int E = E_;
   static constexpr int TT = L / E;
   static constexpr int NT = C * TT;
   static constexpr int NCOL = N * NH;
@@ -134,8 +134,10 @@ struct SP {
 // twiddle table is filled, so a predicated-off launch costs only its dispatch.
 #define SP_SETUP(AXV) SP_SETUP_EXIT(AXV, 0, false)
 #define SP_SETUP_OFF(AXV, OFF) SP_SETUP_EXIT(AXV, OFF, false)
-#define SP_SETUP_EXIT(AXV, OFF, EXIT)                                   \
-  using S = SP<T, N, C, AXV>;                                           \
+#define SP_SETUP_EXIT(AXV, OFF, EXIT) SP_SETUP_EXIT_E(AXV, FftE<N>::value, OFF, EXIT)
+// SP_SETUP_EXIT_E: as SP_SETUP_EXIT with EV values per lane.
+#define SP_SETUP_EXIT_E(AXV, EV, OFF, EXIT)                             \
+  using S = SP<T, N, C, AXV, EV>;                                       \
   constexpr int E = S::E, TT = S::TT, NH = S::NH;                       \
   (void)NH;                                                             \
   __shared__ cx<T> lds[(S::TT > 1) ? N * C : 1];                        \
@@ -150,12 +152,20 @@ struct SP {
 // MODE 0: p is given.  MODE 1: PCG direction p = M r + beta p (stored) and
 // partial |p|^2 (slot 0; Parseval weights).
 // Out: U1 = IFFT_x(s i wx p), U2 = IFFT_x(s p), s = 1/n^3.
+// FP64 at 256^3 keeps 8 values per lane (XInvE): half the registers and
+// twice the waves per SIMD of 16 per lane, for one more LDS exchange per
+// transform.
+template <typename T, int N>
+struct XInvE {
+  static constexpr int value = (sizeof(T) == 8 && N == 256) ? 8 : FftE<N>::value;
+};
+
 template <typename T, int N, int C, int MODE, int OCC>
-__global__ void TG_BOUNDS((SP<T, N, C, 0>::NT), OCC)
+__global__ void TG_BOUNDS((SP<T, N, C, 0, XInvE<T, N>::value>::NT), OCC)
 k_x_inv_grad(cx<T>* __restrict__ P, const cx<T>* __restrict__ Rr, cx<T>* __restrict__ U1,
              cx<T>* __restrict__ U2, const ProbScalars* __restrict__ sc, double* __restrict__ part,
              double tau, int pred) {
-  SP_SETUP_EXIT(0, 0, pred && sc[blockIdx.y].done)
+  SP_SETUP_EXIT_E(0, (XInvE<T, N>::value), 0, pred && sc[blockIdx.y].done)
   __shared__ double red[MODE == 1 ? NSLOT * ((S::NT + 63) / 64) : 1];
   const int ky = gc / NH, kz = gc % NH;
   const T wy = (T)wfull<N>(ky), wz = (T)kz;

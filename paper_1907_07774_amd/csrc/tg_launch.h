@@ -79,12 +79,13 @@ struct SLaunch {
   static void x_inv_grad(int mode, cx<T>* P, const cx<T>* R, cx<T>* U1, cx<T>* U2,
                          const ProbScalars* sc, double* part, double tau, int pred, int nb,
                          hipStream_t st) {
+    using SXI = SP<T, N, C, 0, XInvE<T, N>::value>;
     if (mode == 1)
-      klaunch(k_x_inv_grad<T, N, C, 1, OCC>, dim3(SX::NBLK, nb), dim3(SX::NT), st, P, R, U1, U2, sc, part,
-                                                                           tau, pred);
+      klaunch(k_x_inv_grad<T, N, C, 1, OCC>, dim3(SXI::NBLK, nb), dim3(SXI::NT), st, P, R, U1, U2, sc,
+              part, tau, pred);
     else
-      klaunch(k_x_inv_grad<T, N, C, 0, OCC>, dim3(SX::NBLK, nb), dim3(SX::NT), st, P, R, U1, U2, sc, part,
-                                                                           tau, pred);
+      klaunch(k_x_inv_grad<T, N, C, 0, OCC>, dim3(SXI::NBLK, nb), dim3(SXI::NT), st, P, R, U1, U2, sc,
+              part, tau, pred);
   }
   static void y_inv_grad(cx<T>* U1, cx<T>* U2, cx<T>* V3, const ProbScalars* sc, int pred, int nb,
                          int k, int nslab, hipStream_t st) {
