@@ -152,20 +152,22 @@ struct SP {
 // MODE 0: p is given.  MODE 1: PCG direction p = M r + beta p (stored) and
 // partial |p|^2 (slot 0; Parseval weights).
 // Out: U1 = IFFT_x(s i wx p), U2 = IFFT_x(s p), s = 1/n^3.
-// The x passes of the matvec in FP64 at 256^3 keep 8 values per lane
-// (XPassE): half the registers and twice the waves per SIMD of 16 per lane,
-// for one more LDS exchange per transform.
-template <typename T, int N>
+// The x passes of the matvec in FP64 at 256^3 (up to 32 pencils) keep 8
+// values per lane (XPassE): half the registers and twice the waves per SIMD
+// of 16 per lane, for one more LDS exchange per transform.  (In FP32, 16
+// pencils with 8 values per lane time like 64 pencils with 16, and the
+// whole solve is 0.5% slower with them.)
+template <typename T, int N, int C>
 struct XPassE {
-  static constexpr int value = (sizeof(T) == 8 && N == 256) ? 8 : FftE<N>::value;
+  static constexpr int value = (sizeof(T) == 8 && N == 256 && C <= 32) ? 8 : FftE<N>::value;
 };
 
 template <typename T, int N, int C, int MODE, int OCC>
-__global__ void TG_BOUNDS((SP<T, N, C, 0, XPassE<T, N>::value>::NT), OCC)
+__global__ void TG_BOUNDS((SP<T, N, C, 0, XPassE<T, N, C>::value>::NT), OCC)
 k_x_inv_grad(cx<T>* __restrict__ P, const cx<T>* __restrict__ Rr, cx<T>* __restrict__ U1,
              cx<T>* __restrict__ U2, const ProbScalars* __restrict__ sc, double* __restrict__ part,
              double tau, int pred) {
-  SP_SETUP_EXIT_E(0, (XPassE<T, N>::value), 0, pred && sc[blockIdx.y].done)
+  SP_SETUP_EXIT_E(0, (XPassE<T, N, C>::value), 0, pred && sc[blockIdx.y].done)
   __shared__ double red[MODE == 1 ? NSLOT * ((S::NT + 63) / 64) : 1];
   const int ky = gc / NH, kz = gc % NH;
   const T wy = (T)wfull<N>(ky), wz = (T)kz;
@@ -290,11 +292,11 @@ enum XMode : int {
 };
 
 template <typename T, int N, int C, int MODE, int OCC>
-__global__ void TG_BOUNDS((SP<T, N, C, 0, XPassE<T, N>::value>::NT), OCC)
+__global__ void TG_BOUNDS((SP<T, N, C, 0, XPassE<T, N, C>::value>::NT), OCC)
 k_x_fwd_div(const cx<T>* __restrict__ W1, const cx<T>* __restrict__ W23, cx<T>* __restrict__ X,
             cx<T>* __restrict__ Q, const cx<T>* __restrict__ Sv, const ProbScalars* __restrict__ sc,
             double* __restrict__ part, double tau, int pred, int want_gk) {
-  SP_SETUP_EXIT_E(0, (XPassE<T, N>::value), 0, pred && sc[blockIdx.y].done)
+  SP_SETUP_EXIT_E(0, (XPassE<T, N, C>::value), 0, pred && sc[blockIdx.y].done)
   __shared__ double red[NSLOT * ((S::NT + 63) / 64)];
   const int ky = gc / NH, kz = gc % NH;
   const T wy = (T)wfull<N>(ky), wz = (T)kz;

@@ -79,7 +79,7 @@ struct SLaunch {
   static void x_inv_grad(int mode, cx<T>* P, const cx<T>* R, cx<T>* U1, cx<T>* U2,
                          const ProbScalars* sc, double* part, double tau, int pred, int nb,
                          hipStream_t st) {
-    using SXI = SP<T, N, C, 0, XPassE<T, N>::value>;
+    using SXI = SP<T, N, C, 0, XPassE<T, N, C>::value>;
     if (mode == 1)
       klaunch(k_x_inv_grad<T, N, C, 1, OCC>, dim3(SXI::NBLK, nb), dim3(SXI::NT), st, P, R, U1, U2, sc,
               part, tau, pred);
@@ -102,7 +102,7 @@ struct SLaunch {
   static void x_fwd_div(int mode, const cx<T>* W1, const cx<T>* W23, cx<T>* X, cx<T>* Q,
                         const cx<T>* Sv, const ProbScalars* sc, double* part, double tau, int pred,
                         int want_gk, int nb, hipStream_t st) {
-    using SXF = SP<T, N, C, 0, XPassE<T, N>::value>;
+    using SXF = SP<T, N, C, 0, XPassE<T, N, C>::value>;
     const dim3 g(SXF::NBLK, nb);
     switch (mode) {
       case XM_PCG:
