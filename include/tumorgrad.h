@@ -320,11 +320,18 @@ tg_status tg_stats(tg_plan* plan, tg_solve_stats* out);
  * PCG iteration (1: x-pass inverse with direction update and |p|^2,
  * 2: y-pass inverse, 3: z-pass C2R * m * R2C with the m |grad p|^2 sum,
  * 4: y-pass forward, 5: x-pass forward with the iterate and residual
- * update; 0: off).  While enabled, every launch of that kernel carries a
- * pair of HIP events that take the kernel dispatch's own start and end
- * timestamps (hipExtLaunchKernelGGL): no extra packets on the plan's
- * stream.  tg_kernel_timer resets the counters. */
-tg_status tg_kernel_timer(tg_plan* plan, int kernel_id);
+ * update; 0: off).  While enabled, every launch of that kernel inside the
+ * PCG solves selected by `every` carries a pair of HIP events that take
+ * the kernel dispatch's own start and end timestamps
+ * (hipExtLaunchKernelGGL): no extra packets on the plan's stream.  every
+ * >= 1: the launches of one Crank-Nicolson solve in every (the first, then
+ * every every-th, counted from this call) are timed and only their work is
+ * counted, a uniform sample that keeps the timestamps' cost (a few us of
+ * idle time around each timed dispatch) out of the other solves.  Events
+ * carry no system-scope fence.  tg_kernel_timer resets the counters.
+ * Errors: TG_ERR_ARG (kernel_id out of range, every < 1), TG_ERR_WORKSPACE
+ * (no workspace bound). */
+tg_status tg_kernel_timer(tg_plan* plan, int kernel_id, int every);
 
 /* Streaming reference for the roofline of the PCG passes (measurement
  * only, no part of the method): a kernel that reads five and writes two

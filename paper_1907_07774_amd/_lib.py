@@ -96,7 +96,7 @@ def lib():
     L.tg_plan_destroy.argtypes = [vp]
     L.tg_plan_destroy.restype = None
     L.tg_version.restype = C.c_int
-    L.tg_kernel_timer.argtypes = [vp, C.c_int]
+    L.tg_kernel_timer.argtypes = [vp, C.c_int, C.c_int]
     L.tg_kernel_timer_read.argtypes = [vp, dp, C.POINTER(C.c_longlong), dp]
     L.tg_batch_capture.argtypes = [C.c_int, C.POINTER(vp), C.POINTER(TgBatchIo), C.c_int, vp,
                                    C.POINTER(vp)]

@@ -309,11 +309,12 @@ class Plan:
                                                 C.byref(o)), "tg_plan_get_pass")
         return c.value, o.value
 
-    def kernel_timer(self, name: str | None):
-        """Bracket every launch of one PCG-iteration kernel with HIP events."""
+    def kernel_timer(self, name: str | None, every: int = 1):
+        """Bracket the launches of one PCG-iteration kernel with HIP events,
+        in one Crank-Nicolson solve in `every` (1: all of them)."""
         self._bind()
         kid = 0 if name is None else self.KERNELS[name]
-        _lib.check(_lib.lib().tg_kernel_timer(self._h, kid), "tg_kernel_timer")
+        _lib.check(_lib.lib().tg_kernel_timer(self._h, kid, int(every)), "tg_kernel_timer")
 
     def kernel_timer_read(self):
         """(total ms, launches, algorithmic bytes moved by the timed launches)."""

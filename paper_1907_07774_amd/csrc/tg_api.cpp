@@ -389,10 +389,11 @@ tg_status tg_stats(tg_plan* plan, tg_solve_stats* out) {
   return TG_OK;
 }
 
-tg_status tg_kernel_timer(tg_plan* plan, int kernel_id) {
-  if (plan == nullptr || kernel_id < tg::KT_NONE || kernel_id > tg::KT_LAST) return TG_ERR_ARG;
+tg_status tg_kernel_timer(tg_plan* plan, int kernel_id, int every) {
+  if (plan == nullptr || kernel_id < tg::KT_NONE || kernel_id > tg::KT_LAST || every < 1)
+    return TG_ERR_ARG;
   if (!plan->solver) return TG_ERR_WORKSPACE;
-  return from_hip(plan->solver->timer_enable(kernel_id));
+  return from_hip(plan->solver->timer_enable(kernel_id, every));
 }
 
 tg_status tg_kernel_timer_read(tg_plan* plan, double* total_ms, long long* launches,

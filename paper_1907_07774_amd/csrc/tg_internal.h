@@ -111,7 +111,7 @@ class ISolver {
   // OR of the PCG status bits the host saw during the last call
   virtual int last_status() const = 0;
   // Event timing of one kernel of the PCG iteration (KT_* id; KT_NONE off).
-  virtual hipError_t timer_enable(int id) = 0;
+  virtual hipError_t timer_enable(int id, int every) = 0;
   virtual hipError_t timer_read(double* ms, long long* launches, double* work_bytes) = 0;
   // Transform tile shapes: pencils per x/y workgroup (8, 16, 32), waves
   // per z workgroup (1, 2, 4), x slabs of the y-z-y pass chain (1, 2, 4, 8)

@@ -453,6 +453,8 @@ class Solver final : public ISolver {
   // x0 from one matvec on d (XM_SHIFT); 2 keeps this step's d for the next.
   hipError_t step_solve(const Ctx& c, bool adj, int est = -1, bool exact = false,
                         int hist = 0) {
+    // kernel timer: this solve's launches are timed if it is a sampled one
+    tm_on_ = tm_id_ == KT_NONE || tm_solves_++ % tm_every_ == 0;
     sch_.y_plain(false, c.T1, adj ? c.S : nullptr, c.nb, st_);
     TG_LAUNCH_CHECK();
     sch_.x_fwd_state(c.T1, c.X, c.T2, c.T3, adj ? c.S : nullptr, c.nb, st_);
@@ -547,11 +549,17 @@ class Solver final : public ISolver {
   }
 
  public:
-  hipError_t timer_enable(int id) override {
+  hipError_t timer_enable(int id, int every) override {
     TG_CHECK(timer_flush());
+    tm_every_ = every;
+    tm_solves_ = 0;
+    tm_on_ = true;
     if (tm_ev_.empty()) {
       tm_ev_.resize(2 * TM_CAP);
-      for (auto& e : tm_ev_) TG_CHECK(hipEventCreate(&e));
+      // timing-only events: no system-scope fence (its L2 write-back and
+      // invalidate around every timed dispatch left gaps of about 5 us
+      // before and after it)
+      for (auto& e : tm_ev_) TG_CHECK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     }
     tm_id_ = id;
     tm_ms_ = 0.0;
@@ -573,7 +581,7 @@ class Solver final : public ISolver {
   static constexpr int TM_CAP = 1024;
   template <class F>
   void timed(int id, int work, F&& launch) {
-    if (id != tm_id_) {
+    if (id != tm_id_ || !tm_on_) {
       launch();
       return;
     }
@@ -651,7 +659,7 @@ class Solver final : public ISolver {
     its_max_call_ = std::max(its_max_call_, maxseen);
     rec_.push_back(maxseen);
     ++seq_;
-    if (tm_id_ != KT_NONE) {
+    if (tm_id_ != KT_NONE && tm_on_) {
       long long eff = 0;
       for (int b = 0; b < c.nb; ++b) eff += hsc_[b].its;
       tm_work_ += eff;
@@ -943,6 +951,9 @@ class Solver final : public ISolver {
   int stat_nb_ = 0;
   // kernel timer state
   int tm_id_ = KT_NONE;
+  int tm_every_ = 1;         // time the launches of one solve in tm_every_
+  long long tm_solves_ = 0;  // solves since the timer was enabled
+  bool tm_on_ = true;        // the current solve's launches are timed
   std::vector<hipEvent_t> tm_ev_;
   int tm_used_ = 0;
   double tm_ms_ = 0.0;

@@ -96,6 +96,11 @@ def test_schedule_calls_need_a_bound_plan():
     assert L.tg_plan_get_pass(h, 1, C.byref(c), C.byref(o)) == _lib.TG_ERR_WORKSPACE
     assert L.tg_plan_set_pass(None, 1, 16, 1) == _lib.TG_ERR_ARG
     assert L.tg_plan_get_pass(h, 1, None, C.byref(o)) == _lib.TG_ERR_ARG
+    # kernel timer: argument checks before the workspace check
+    assert L.tg_kernel_timer(h, 3, 0) == _lib.TG_ERR_ARG
+    assert L.tg_kernel_timer(h, 99, 1) == _lib.TG_ERR_ARG
+    assert L.tg_kernel_timer(None, 3, 1) == _lib.TG_ERR_ARG
+    assert L.tg_kernel_timer(h, 3, 8) == _lib.TG_ERR_WORKSPACE
     L.tg_plan_destroy(h)
 
 
