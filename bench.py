@@ -74,16 +74,18 @@ def parse():
 
 
 def kernel_source_hash():
+    """Hash of the transform kernels' sources and of the schedule cache
+    (which picks the kernel instantiation the bench times)."""
     h = hashlib.sha256()
-    for f in ("tg_kernels.h", "tg_fft.h"):
-        with open(os.path.join(ROOT, "paper_1907_07774_amd", "csrc", f), "rb") as fh:
+    for f in ("csrc/tg_kernels.h", "csrc/tg_fft.h", "csrc/tg_launch.h", "schedules.json"):
+        with open(os.path.join(ROOT, "paper_1907_07774_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
 def load_traffic(kernel, n, prec):
     """Measured HBM bytes per launch from the committed counter summary, if
-    it was taken on the current kernel sources."""
+    it was taken on the current kernel sources and schedules."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as fh:
