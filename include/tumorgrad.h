@@ -305,7 +305,9 @@ tg_status tg_plan_get_schedule(const tg_plan* plan, int* pencils, int* z_waves, 
  * above.  For the z matvec, pencils selects the layout of a spectral row in
  * registers: 8 for one complex value per lane access, 16 for a pair
  * (16-byte accesses in FP32), 0 for the default (16 in FP32, 8 in FP64);
- * z_waves 8 allows neither.  Results are identical up to the summation
+ * under z_waves 8 (the wide z matvec, no per-pass variant) only the shape
+ * tg_plan_get_pass reports is accepted, as a no-op, so a plan's passes can
+ * be copied to another plan.  Results are identical up to the summation
  * order of the FP64 partial sums.  Errors: TG_ERR_ARG for an unknown pass
  * or value (the plan keeps its schedule), TG_ERR_WORKSPACE before
  * tg_plan_bind. */

@@ -117,7 +117,9 @@ class Solver final : public ISolver {
     Sched<T, N> s = sch_;
     if (id == KT_Z_MATVEC) {
       if (C == 0) C = kZPairDefault ? 16 : 8;
-      if ((C != 8 && C != 16) || zwaves_ == 8) return false;
+      // the wide z matvec has no per-pass variant: its own shape is a no-op
+      if (zwaves_ == 8) return C == pass_C_[id] && occ == pass_occ_[id];
+      if (C != 8 && C != 16) return false;
       if (!set_zrows<T, N>(s, zwaves_, occ, true, C == 16)) return false;
     } else {
       if (!set_strided<T, N>(s, C, occ, id)) return false;

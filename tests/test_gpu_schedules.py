@@ -128,3 +128,5 @@ def test_schedule_errors():
     assert plan.get_pass("z_matvec") == (8, 1)
     with pytest.raises(_lib.TumorGradError):
         plan.set_pass("z_matvec", 0, 4)  # the wide z matvec has no per-pass variant
+    plan.set_pass("z_matvec", *plan.get_pass("z_matvec"))  # its own shape: a no-op
+    assert plan.get_pass("z_matvec") == (8, 1)
