@@ -105,6 +105,34 @@ def test_per_pass_fp32_agrees():
     assert rel(a, b) < 1e-5
 
 
+def test_kernel_timer_samples_solves():
+    """The kernel timer with every = k times the launches of one
+    Crank-Nicolson solve in k (the first, then every k-th) and counts only
+    their work: fewer timed launches, the same time per launch that did
+    work, and every < 1 is an argument error."""
+    print("case kernel timer sampling n=32", flush=True)
+    pr, p = problem(32)
+    nt = 8
+    plan = api.Plan(32, nt, pr.centres, pr.sigma, rtol=1e-10, precision="fp64")
+    plan.forward(p, pr.rho_f, pr.k_f, pr.m)
+    out = {}
+    for every in (1, 4, 100):
+        plan.kernel_timer("z_matvec", every)
+        plan.forward(p, pr.rho_f, pr.k_f, pr.m)
+        out[every] = plan.kernel_timer_read()
+    plan.kernel_timer(None)
+    ms1, n1, b1 = out[1]
+    ms4, n4, b4 = out[4]
+    ms100, n100, b100 = out[100]
+    assert n1 > n4 > 0 and b1 > b4 > 0
+    # every 4th of the nt forward solves (and the right-hand-side matvecs of
+    # those solves), so between a sixth and a half of the launches
+    assert n1 / 6 < n4 < n1 / 2
+    assert 0 < n100 < n4  # only the first solve
+    with pytest.raises(_lib.TumorGradError):
+        plan.kernel_timer("z_matvec", 0)
+
+
 def test_schedule_errors():
     print("case schedule errors", flush=True)
     pr, p = problem(32)

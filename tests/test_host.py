@@ -56,3 +56,44 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
+
+
+class _FakePlan:
+    """Stands in for api.Plan in the schedule search: passes as a dict, and
+    the wide z matvec (z_waves 8) accepting only its own shape, as the
+    library does."""
+
+    def __init__(self, zw):
+        self.zw = zw
+        self.passes = {k: (32, 1) for k in autotune.PASSES}
+        self.passes["z_matvec"] = (8, 1)
+
+    def get_schedule(self):
+        return (32, self.zw, 1, 1)
+
+    def get_pass(self, k):
+        return self.passes[k]
+
+    def set_pass(self, k, c, o):
+        if k == "z_matvec" and self.zw == 8 and (c, o) != self.passes[k]:
+            raise RuntimeError("the wide z matvec has no per-pass variant")
+        self.passes[k] = (c, o)
+
+
+def test_pass_search_with_and_without_the_wide_z_matvec(monkeypatch):
+    # forward time: 100 ms, 5 less with x_inv_grad at (16, 4), 2 less with
+    # the z matvec in pairs
+    def fake_time(plan, args, reps):
+        return (100.0 - (5.0 if plan.passes["x_inv_grad"] == (16, 4) else 0.0)
+                - (2.0 if plan.passes["z_matvec"] == (16, 1) else 0.0))
+    monkeypatch.setattr(autotune, "_median_forward", fake_time)
+    for zw in (2, 8):
+        plan = _FakePlan(zw)
+        passes, before, after = autotune.tune_passes(plan, None, None, None, None)
+        assert before == 100.0
+        assert passes["x_inv_grad"] == (16, 4)
+        if zw == 8:
+            assert "z_matvec" not in passes and after == 95.0
+            assert plan.passes["z_matvec"] == (8, 1)
+        else:
+            assert passes["z_matvec"] == (16, 1) and after == 93.0
