@@ -74,12 +74,16 @@ def parse():
 
 
 def kernel_source_hash():
-    """Hash of the transform kernels' sources and of the schedule cache
-    (which picks the kernel instantiation the bench times)."""
+    """Hash of the transform kernels' sources and of the 256^3 FP32
+    schedule-cache entry (which picks the kernel instantiation the bench
+    times)."""
     h = hashlib.sha256()
-    for f in ("csrc/tg_kernels.h", "csrc/tg_fft.h", "csrc/tg_launch.h", "schedules.json"):
+    for f in ("csrc/tg_kernels.h", "csrc/tg_fft.h", "csrc/tg_launch.h"):
         with open(os.path.join(ROOT, "paper_1907_07774_amd", f), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(ROOT, "paper_1907_07774_amd", "schedules.json")) as fh:
+        ent = json.load(fh).get("gfx950/n256/fp32/b1")
+    h.update(json.dumps(ent, sort_keys=True).encode())
     return h.hexdigest()[:16]
 
 
